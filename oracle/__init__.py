@@ -1,0 +1,196 @@
+"""CPU FP64 oracle for the Diffusing Winding Gradients hot path (arXiv 2405.13839).
+
+TEST INFRASTRUCTURE ONLY: the slow, plain definition that the GPU library is checked
+against. Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import it. It shares no code with ``paper_2405_13839_amd`` and never
+calls it; the GPU library never imports this package.
+
+The arithmetic lives in ``dwg_oracle.c`` (plain C, double precision, Neumaier sums,
+OpenMP over independent queries) and ``mlp.py`` (NumPy float64). This module is the
+ctypes binding: it promotes the caller's FP32 arrays exactly to float64 and returns
+float64 results.
+
+Parity pins (closed forms, finite differences, invariants, published test vectors,
+library special cases) are in ``tests/test_oracle_*.py``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dwg_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile dwg_oracle.c with gcc (-O2 -fopenmp, no fast-math) into liboracle.so."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int32)
+        i64 = ctypes.c_int64
+        lib.orc_gwn.argtypes = [dp, dp, dp, dp, i64, dp, i64, ctypes.c_double, ctypes.c_double, dp, dp, ip]
+        lib.orc_update.argtypes = [dp, dp, i64, dp, dp]
+        lib.orc_stats.argtypes = [dp, dp, i64, ctypes.c_double, dp]
+        lib.orc_top_count.argtypes = [i64, ctypes.c_double]
+        lib.orc_top_count.restype = i64
+        lib.orc_dwg_run.argtypes = [dp, dp, dp, i64, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
+        lib.orc_knn_self.argtypes = [dp, i64, ctypes.c_int, ip, dp]
+        lib.orc_knn.argtypes = [dp, i64, dp, i64, ip, ctypes.c_int, ip, dp]
+        lib.orc_delta.argtypes = [dp, i64, ctypes.c_int, dp]
+        lib.orc_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        lib.orc_splitmix64.restype = ctypes.c_uint64
+        lib.orc_random_normals.argtypes = [ctypes.c_uint64, i64, dp]
+        lib.orc_num_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _d(a, shape=None):
+    """Contiguous float64 copy (exact promotion of FP32 inputs)."""
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape is not None and a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def _p(a, ct=ctypes.c_double):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+def gwn(P, N, area, delta, Q, lam=0.0, eps=0.0, grad=True):
+    """w[m], grad w [3,m] (or None) and flags[m] of the (screened, clamped) GWN at Q.
+
+    P, N: [3,n] sources and normals; area: [n]; delta: [n] or None; Q: [3,m].
+    """
+    lib = _load()
+    P = _d(P)
+    n = P.shape[1]
+    N = _d(N, (3, n))
+    area = _d(area, (n,))
+    delta = None if delta is None else _d(delta, (n,))
+    Q = _d(Q)
+    m = Q.shape[1]
+    w = np.zeros(m)
+    g = np.zeros((3, m)) if grad else None
+    fl = np.zeros(m, dtype=np.int32)
+    rc = lib.orc_gwn(_p(P), _p(N), _p(area), _p(delta), n, _p(Q), m, float(lam), float(eps), _p(w), _p(g),
+                     _p(fl, ctypes.c_int32))
+    if rc != 0:
+        raise ValueError("orc_gwn rejected its arguments")
+    return w, g, fl
+
+
+def update(g, N_old):
+    """Eq. 7 point-wise: (N_new [3,n], chord [n])."""
+    lib = _load()
+    g = _d(g)
+    n = g.shape[1]
+    N_old = _d(N_old, (3, n))
+    N_new = np.zeros((3, n))
+    ch = np.zeros(n)
+    lib.orc_update(_p(g), _p(N_old), n, _p(N_new), _p(ch))
+    return N_new, ch
+
+
+def top_count(n: int, top_frac: float = 0.01) -> int:
+    return int(_load().orc_top_count(n, top_frac))
+
+
+def stats(w, chord, top_frac=0.01):
+    """(wmean, top_mean_deg, mean_chord)."""
+    lib = _load()
+    w = _d(w)
+    chord = _d(chord, w.shape)
+    out = np.zeros(3)
+    rc = lib.orc_stats(_p(w), _p(chord), w.shape[0], float(top_frac), _p(out))
+    if rc != 0:
+        raise ValueError("orc_stats rejected its arguments")
+    return float(out[0]), float(out[1]), float(out[2])
+
+
+def dwg_run(P, area, delta, N0, lam=0.0, eps=0.0, max_iters=30, fixed_iters=True, eps_deg=0.1,
+            top_frac=0.01):
+    """Algorithm 1 (point-wise, Jacobi). Returns (N_final [3,n], stats [T,3])."""
+    lib = _load()
+    P = _d(P)
+    n = P.shape[1]
+    area = _d(area, (n,))
+    delta = None if delta is None else _d(delta, (n,))
+    N = _d(N0, (3, n)).copy()
+    st = np.zeros((max_iters, 3))
+    done = lib.orc_dwg_run(_p(P), _p(area), _p(delta), n, _p(N), float(lam), float(eps), int(max_iters),
+                           int(bool(fixed_iters)), float(eps_deg), float(top_frac), _p(st))
+    if done < 1:
+        raise RuntimeError("orc_dwg_run failed (%d)" % done)
+    return N, st[:done]
+
+
+def knn_self(P, k):
+    """k nearest other points of every point: (idx int32 [n,k], dist float64 [n,k])."""
+    lib = _load()
+    P = _d(P)
+    n = P.shape[1]
+    idx = np.zeros((n, k), dtype=np.int32)
+    dist = np.zeros((n, k))
+    if lib.orc_knn_self(_p(P), n, int(k), _p(idx, ctypes.c_int32), _p(dist)) != 0:
+        raise ValueError("orc_knn_self rejected its arguments")
+    return idx, dist
+
+
+def knn(R, Q, k, skip=None):
+    """k nearest points of R for each query of Q, skipping R[skip[i]] for query i."""
+    lib = _load()
+    R = _d(R)
+    Q = _d(Q)
+    m = Q.shape[1]
+    sk = None if skip is None else np.ascontiguousarray(np.asarray(skip, dtype=np.int32))
+    idx = np.zeros((m, k), dtype=np.int32)
+    dist = np.zeros((m, k))
+    if lib.orc_knn(_p(R), R.shape[1], _p(Q), m, _p(sk, ctypes.c_int32), int(k), _p(idx, ctypes.c_int32),
+                   _p(dist)) != 0:
+        raise ValueError("orc_knn rejected its arguments")
+    return idx, dist
+
+
+def delta(P, k=10):
+    """delta_i = mean distance to the k nearest other points [n]."""
+    lib = _load()
+    P = _d(P)
+    n = P.shape[1]
+    out = np.zeros(n)
+    if lib.orc_delta(_p(P), n, int(k), _p(out)) != 0:
+        raise ValueError("orc_delta rejected its arguments")
+    return out
+
+
+def splitmix64(seed: int, t: int) -> int:
+    return int(_load().orc_splitmix64(ctypes.c_uint64(seed), ctypes.c_uint64(t)))
+
+
+def random_normals(seed: int, n: int):
+    lib = _load()
+    out = np.zeros((3, n))
+    lib.orc_random_normals(ctypes.c_uint64(seed), n, _p(out))
+    return out

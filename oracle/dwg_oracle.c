@@ -1,0 +1,361 @@
+/*
+ * dwg_oracle.c -- CPU FP64 reference ("oracle") for the Diffusing Winding Gradients
+ * hot path (Liu et al., "Diffusing Winding Gradients (DWG)", arXiv 2405.13839).
+ *
+ * TEST INFRASTRUCTURE ONLY. This file is the slow, plain, obviously-correct definition
+ * the GPU library is checked against. Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load it. It shares no code, header, table or
+ * constant generator with the GPU library (paper_2405_13839_amd/csrc), and the GPU
+ * library never loads it.
+ *
+ * Arithmetic: the API takes double arrays; callers pass the FP32 inputs the GPU gets,
+ * promoted exactly to double. All arithmetic is double; sums over sources use a Neumaier compensated sum in source-index order.
+ * Compile with -O2 -fopenmp and WITHOUT -ffast-math. OpenMP parallelises over
+ * independent queries only, so results do not depend on the thread count.
+ *
+ * Functions and the passages they follow:
+ *   orc_gwn          -- discrete GWN dipole sum (Sec. 3, Eq. 2-3), its screened form
+ *                       (Sec. 4.2, Eq. 5), the modified Poisson kernel with per-source
+ *                       threshold delta (Sec. 5.2, "Poisson Kernels"), the "small constant"
+ *                       in the denominator (Sec. 3, after Eq. 3), and the gradient with
+ *                       respect to the query with the normals held fixed (Sec. 4.1).
+ *   orc_update       -- normal update n <- normalize(-grad w) (Sec. 4.3, Eq. 7), keeping the
+ *                       old normal when the gradient is zero (Sec. 4.3, empty face set).
+ *   orc_stats        -- mean GWN over the input points (Sec. 4.3, Eq. 6) and the
+ *                       convergence statistic: mean of the top 1% of normal changes
+ *                       (Sec. 5.1, "Model-independent Parameters").
+ *   orc_dwg_run      -- the iteration of Algorithm 1 with the point-wise update above.
+ *   orc_knn_self     -- brute-force k nearest neighbours (Sec. 5.1 uses kNN for delta).
+ *   orc_delta        -- delta_i = mean distance to the k nearest other points.
+ *   orc_random_normals -- i.i.d. uniform unit normals (Algorithm 1 initialisation) from a
+ *                       counter-based SplitMix64 stream (Steele, Lea, Flood, OOPSLA 2014).
+ *
+ * Readings where the paper is silent are listed with the reasons in the design notes:
+ *   - update sign: n <- -grad w / |grad w| (w is 1 inside for outward normals, so grad w
+ *     points inward near the surface);
+ *   - a pair with p_j == q exactly contributes nothing (self pair at an input point);
+ *   - rho = max(r, delta_j, eps) only replaces the cube in the denominator; the screening
+ *     factor uses the true r; the gradient is the derivative of that piecewise function;
+ *   - a query is flagged when |r - max(delta_j, eps)| <= 1e-6 * max(delta_j, eps) for some
+ *     source, because there an FP32 evaluation may take the other branch of the clamp.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ---------------------------------------------------------------- compensated sums */
+typedef struct {
+  double s, c;
+} nsum;
+
+static inline void nadd(nsum* a, double x) {
+  /* Neumaier's improvement of Kahan summation (Neumaier 1974). */
+  double t = a->s + x;
+  if (fabs(a->s) >= fabs(x))
+    a->c += (a->s - t) + x;
+  else
+    a->c += (x - t) + a->s;
+  a->s = t;
+}
+static inline double nval(const nsum* a) { return a->s + a->c; }
+
+int orc_version(void) { return 1; }
+
+/* ------------------------------------------------------------------------- GWN
+ * P, Nrm: sources, planar [3][n] (x block, then y, then z).  A: area weights [n].
+ * D: per-source delta [n] or NULL (= all zero).  Q: queries [3][m].
+ * lambda >= 0 (screening), eps >= 0 (global floor on the kernel radius).
+ * Outputs: w[m]; g[3][m] (may be NULL); flag[m] (may be NULL).
+ *
+ * For one (query q, source j):  d = p_j - q, r = |d|;  if r == 0 the pair is skipped.
+ *   rho = max(r, delta_j, eps), s = sqrt(lambda), E = exp(-s r), phi = E (1 + s r),
+ *   c = <d, n_j>, k = a_j / (4 pi)
+ *   w      += k phi c / rho^3                                   (Eq. 5; Eq. 2-3 at s = 0)
+ *   grad w += k E [ (3 (1 + s r) / r^2 [rho == r] + s^2) c d - (1 + s r) n_j ] / rho^3
+ * The gradient line is d/dq of the w line: d/dq c = -n_j, d/dq r = -d / r,
+ * d/dr phi = -s^2 r E, and d/dq rho^-3 = 3 d / r^5 only when rho == r.
+ */
+int orc_gwn(const double* P, const double* Nrm, const double* A, const double* D, int64_t n,
+            const double* Q, int64_t m, double lambda, double eps, double* w, double* g,
+            int32_t* flag) {
+  if (!P || !Nrm || !A || !Q || !w || n < 0 || m < 0 || !(lambda >= 0.0) || !(eps >= 0.0))
+    return -1;
+  const double s = sqrt(lambda);
+  const double inv4pi = 1.0 / (4.0 * M_PI);
+  int64_t i;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (i = 0; i < m; ++i) {
+    const double qx = Q[i], qy = Q[m + i], qz = Q[2 * m + i];
+    nsum sw = {0, 0}, sgx = {0, 0}, sgy = {0, 0}, sgz = {0, 0};
+    int32_t fl = 0;
+    for (int64_t j = 0; j < n; ++j) {
+      const double dx = P[j] - qx, dy = P[n + j] - qy, dz = P[2 * n + j] - qz;
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (r2 == 0.0) continue;
+      const double r = sqrt(r2);
+      double floor_j = D ? D[j] : 0.0;
+      if (eps > floor_j) floor_j = eps;
+      const double rho = r > floor_j ? r : floor_j;
+      if (floor_j > 0.0 && fabs(r - floor_j) <= 1e-6 * floor_j) fl = 1;
+      const double nx = Nrm[j], ny = Nrm[n + j], nz = Nrm[2 * n + j];
+      const double k = A[j] * inv4pi;
+      const double sr = s * r;
+      const double E = exp(-sr);
+      const double phi = E * (1.0 + sr);
+      const double c = dx * nx + dy * ny + dz * nz;
+      const double rho3 = rho * rho * rho;
+      nadd(&sw, k * phi * c / rho3);
+      if (g) {
+        const double coef = (rho == r ? 3.0 * (1.0 + sr) / r2 : 0.0) + s * s;
+        const double f = k * E / rho3;
+        nadd(&sgx, f * (coef * c * dx - (1.0 + sr) * nx));
+        nadd(&sgy, f * (coef * c * dy - (1.0 + sr) * ny));
+        nadd(&sgz, f * (coef * c * dz - (1.0 + sr) * nz));
+      }
+    }
+    w[i] = nval(&sw);
+    if (g) {
+      g[i] = nval(&sgx);
+      g[m + i] = nval(&sgy);
+      g[2 * m + i] = nval(&sgz);
+    }
+    if (flag) flag[i] = fl;
+  }
+  return 0;
+}
+
+/* ---------------------------------------------------------------------- update
+ * Eq. 7 with the point-wise gradient: n_new = -g / |g|; when |g| is zero or not finite the
+ * point keeps its normal. chord[i] = |n_new - n_old|. Nold and Nnew are [3][n] doubles.
+ */
+int orc_update(const double* g, const double* Nold, int64_t n, double* Nnew, double* chord) {
+  if (!g || !Nold || !Nnew || n < 0) return -1;
+  for (int64_t i = 0; i < n; ++i) {
+    const double gx = g[i], gy = g[n + i], gz = g[2 * n + i];
+    const double len = sqrt(gx * gx + gy * gy + gz * gz);
+    double x = Nold[i], y = Nold[n + i], z = Nold[2 * n + i];
+    if (len > 0.0 && isfinite(len)) {
+      x = -gx / len;
+      y = -gy / len;
+      z = -gz / len;
+    }
+    if (chord) {
+      const double ex = x - Nold[i], ey = y - Nold[n + i], ez = z - Nold[2 * n + i];
+      chord[i] = sqrt(ex * ex + ey * ey + ez * ez);
+    }
+    Nnew[i] = x;
+    Nnew[n + i] = y;
+    Nnew[2 * n + i] = z;
+  }
+  return 0;
+}
+
+static int cmp_desc(const void* a, const void* b) {
+  const double x = *(const double*)a, y = *(const double*)b;
+  return (x < y) - (x > y);
+}
+
+/* Number of largest normal changes averaged by the convergence test: ceil(top_frac * n),
+ * at least 1 and at most n. */
+int64_t orc_top_count(int64_t n, double top_frac) {
+  int64_t k = (int64_t)ceil(top_frac * (double)n);
+  if (k < 1) k = 1;
+  if (k > n) k = n;
+  return k;
+}
+
+/* ----------------------------------------------------------------------- stats
+ * wmean = (1/n) sum w_i (Eq. 6 over the input points).
+ * theta_i = 2 asin(min(1, chord_i / 2)) in degrees (the angle between consecutive normals);
+ * top_mean_deg = mean of the ceil(top_frac n) largest theta_i (full sort);
+ * mean_chord = (1/n) sum chord_i.
+ */
+int orc_stats(const double* w, const double* chord, int64_t n, double top_frac, double* out3) {
+  if (!w || !chord || !out3 || n <= 0 || !(top_frac > 0.0 && top_frac <= 1.0)) return -1;
+  nsum sw = {0, 0}, sc = {0, 0};
+  double* th = (double*)malloc(sizeof(double) * (size_t)n);
+  if (!th) return -2;
+  for (int64_t i = 0; i < n; ++i) {
+    nadd(&sw, w[i]);
+    nadd(&sc, chord[i]);
+    const double h = chord[i] * 0.5;
+    th[i] = 2.0 * asin(h < 1.0 ? h : 1.0) * (180.0 / M_PI);
+  }
+  qsort(th, (size_t)n, sizeof(double), cmp_desc);
+  const int64_t k = orc_top_count(n, top_frac);
+  nsum st = {0, 0};
+  for (int64_t i = 0; i < k; ++i) nadd(&st, th[i]);
+  out3[0] = nval(&sw) / (double)n;
+  out3[1] = nval(&st) / (double)k;
+  out3[2] = nval(&sc) / (double)n;
+  free(th);
+  return 0;
+}
+
+/* -------------------------------------------------------------------- DWG run
+ * Algorithm 1 with every input point as a query: for t = 1..max_iters
+ *   evaluate w, grad w at every p_i with the normals n^(t-1) (Jacobi: one field per
+ *   iteration), update all normals, compute the stats, and stop when
+ *   top_mean_deg <= eps_deg unless fixed_iters is set.
+ * The normals are kept in double between iterations (the oracle never rounds them).
+ * N_inout: [3][n] doubles, n^(0) in, n^(T) out. stats: [max_iters][3] or NULL.
+ * Returns the number of iterations done (>= 1) or a negative error.
+ */
+int orc_dwg_run(const double* P, const double* A, const double* D, int64_t n, double* N_inout,
+                double lambda, double eps, int max_iters, int fixed_iters, double eps_deg,
+                double top_frac, double* stats) {
+  if (!P || !A || !N_inout || n <= 0 || max_iters < 1) return -1;
+  const size_t n3 = 3 * (size_t)n;
+  double* w = (double*)malloc(sizeof(double) * (size_t)n);
+  double* g = (double*)malloc(sizeof(double) * n3);
+  double* nn = (double*)malloc(sizeof(double) * n3);
+  double* ch = (double*)malloc(sizeof(double) * (size_t)n);
+  int done = -2;
+  if (w && g && nn && ch) {
+    for (int t = 0; t < max_iters; ++t) {
+      orc_gwn(P, N_inout, A, D, n, P, n, lambda, eps, w, g, NULL);
+      orc_update(g, N_inout, n, nn, ch);
+      memcpy(N_inout, nn, sizeof(double) * n3);
+      double st[3];
+      orc_stats(w, ch, n, top_frac, st);
+      if (stats) memcpy(stats + 3 * (size_t)t, st, sizeof st);
+      done = t + 1;
+      if (!fixed_iters && st[1] <= eps_deg) break;
+    }
+  }
+  free(w); free(g); free(nn); free(ch);
+  return done;
+}
+
+/* ---------------------------------------------------------- k nearest neighbours
+ * For every point i of P ([3][n]) the k nearest OTHER points j != i by Euclidean distance
+ * computed in double; equal distances are ordered by index. idx[i*k + t], dist[i*k + t]
+ * in ascending order. Requires k <= n - 1. Brute force, O(n^2).
+ */
+int orc_knn_self(const double* P, int64_t n, int k, int32_t* idx, double* dist) {
+  if (!P || !idx || !dist || k < 1 || n < 2 || (int64_t)k > n - 1) return -1;
+  int64_t i;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (i = 0; i < n; ++i) {
+    double bd[64];
+    int32_t bi[64];
+    int cnt = 0;
+    const double qx = P[i], qy = P[n + i], qz = P[2 * n + i];
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      const double dx = P[j] - qx, dy = P[n + j] - qy, dz = P[2 * n + j] - qz;
+      const double d = sqrt(dx * dx + dy * dy + dz * dz);
+      if (cnt == k && !(d < bd[k - 1])) continue; /* ties keep the lower index */
+      int pos = cnt < k ? cnt++ : k - 1;
+      while (pos > 0 && bd[pos - 1] > d) {
+        bd[pos] = bd[pos - 1];
+        bi[pos] = bi[pos - 1];
+        --pos;
+      }
+      bd[pos] = d;
+      bi[pos] = (int32_t)j;
+    }
+    for (int t = 0; t < k; ++t) {
+      idx[i * k + t] = bi[t];
+      dist[i * k + t] = bd[t];
+    }
+  }
+  return 0;
+}
+
+/* k nearest points of a separate reference set R ([3][nr]) for each query of Q ([3][m]),
+ * skipping the reference point whose index equals skip[i] (pass NULL to skip none). */
+int orc_knn(const double* R, int64_t nr, const double* Q, int64_t m, const int32_t* skip, int k,
+            int32_t* idx, double* dist) {
+  if (!R || !Q || !idx || !dist || k < 1 || k > 64 || nr < k + (skip ? 1 : 0)) return -1;
+  int64_t i;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (i = 0; i < m; ++i) {
+    double bd[64];
+    int32_t bi[64];
+    int cnt = 0;
+    const double qx = Q[i], qy = Q[m + i], qz = Q[2 * m + i];
+    for (int64_t j = 0; j < nr; ++j) {
+      if (skip && skip[i] == (int32_t)j) continue;
+      const double dx = R[j] - qx, dy = R[nr + j] - qy, dz = R[2 * nr + j] - qz;
+      const double d = sqrt(dx * dx + dy * dy + dz * dz);
+      if (cnt == k && !(d < bd[k - 1])) continue;
+      int pos = cnt < k ? cnt++ : k - 1;
+      while (pos > 0 && bd[pos - 1] > d) {
+        bd[pos] = bd[pos - 1];
+        bi[pos] = bi[pos - 1];
+        --pos;
+      }
+      bd[pos] = d;
+      bi[pos] = (int32_t)j;
+    }
+    for (int t = 0; t < k; ++t) {
+      idx[i * k + t] = bi[t];
+      dist[i * k + t] = bd[t];
+    }
+  }
+  return 0;
+}
+
+/* delta_i = mean distance from p_i to its k nearest other points (Sec. 5.2 threshold,
+ * without the absolute distance filter). */
+int orc_delta(const double* P, int64_t n, int k, double* delta) {
+  if (!P || !delta || k < 1 || k > 64 || n < k + 1) return -1;
+  int32_t* idx = (int32_t*)malloc(sizeof(int32_t) * (size_t)n * (size_t)k);
+  double* dist = (double*)malloc(sizeof(double) * (size_t)n * (size_t)k);
+  if (!idx || !dist) {
+    free(idx); free(dist);
+    return -2;
+  }
+  orc_knn_self(P, n, k, idx, dist);
+  for (int64_t i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int t = 0; t < k; ++t) s += dist[i * k + t];
+    delta[i] = s / (double)k;
+  }
+  free(idx); free(dist);
+  return 0;
+}
+
+/* ---------------------------------------------------------------- random normals
+ * SplitMix64: output number t (t = 0, 1, ...) of the stream started at `seed` is
+ * mix(seed + (t + 1) * 0x9e3779b97f4a7c15) with the published finaliser mix.
+ * Point i uses outputs 2i and 2i+1; u = (x >> 40) * 2^-24 is uniform on [0,1) with 24 bits.
+ * Uniform direction (Archimedes' hat-box theorem): z = 1 - 2 u0, phi = 2 pi u1,
+ * n = (sqrt(1 - z^2) cos phi, sqrt(1 - z^2) sin phi, z).
+ */
+uint64_t orc_splitmix64(uint64_t seed, uint64_t t) {
+  uint64_t z = seed + (t + 1) * 0x9e3779b97f4a7c15ULL;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+
+int orc_random_normals(uint64_t seed, int64_t n, double* Nout) {
+  if (!Nout || n < 0) return -1;
+  for (int64_t i = 0; i < n; ++i) {
+    const double u0 = (double)(orc_splitmix64(seed, 2 * (uint64_t)i) >> 40) * (1.0 / 16777216.0);
+    const double u1 = (double)(orc_splitmix64(seed, 2 * (uint64_t)i + 1) >> 40) * (1.0 / 16777216.0);
+    const double z = 1.0 - 2.0 * u0;
+    const double ph = 2.0 * M_PI * u1;
+    const double rr = sqrt(fmax(0.0, 1.0 - z * z));
+    Nout[i] = rr * cos(ph);
+    Nout[n + i] = rr * sin(ph);
+    Nout[2 * n + i] = z;
+  }
+  return 0;
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  extern int omp_get_max_threads(void);
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

@@ -1,0 +1,261 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these re-type the oracle's kernel: they check it against closed-form integrals
+(Gauss / solid-angle result and the Yukawa double layer on a sphere), central finite
+differences, symmetries, a published RNG test vector and library routines.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_13839_amd import synth
+
+
+def _sphere_q():
+    # interior and exterior query points at least 0.3 from the unit sphere
+    return np.array([[0, 0, 0], [0.3, 0.2, -0.1], [0, 0, 0.6], [-0.4, 0.3, 0.2],
+                     [1.5, 0, 0], [0, 2, 0], [1.2, 0.9, 0.3], [-1.0, -1.0, 1.0]], dtype=np.float64).T
+
+
+@pytest.fixture(scope="module")
+def fib():
+    return synth.fibonacci_sphere(20000)
+
+
+def test_plain_sphere_is_indicator(fib):
+    """Eq. 1-2: with exact outward normals w = 1 inside, 0 outside, grad w = 0 off the surface."""
+    Q = _sphere_q()
+    w, g, fl = oracle.gwn(fib.P, fib.N_true, fib.area, None, Q)
+    rho = np.linalg.norm(Q, axis=0)
+    np.testing.assert_allclose(w, np.where(rho < 1, 1.0, 0.0), atol=1e-5)
+    assert np.max(np.linalg.norm(g, axis=0)) < 1e-3
+    assert not fl.any()
+
+
+def test_plain_sphere_surface_half(fib):
+    """At a sample point (self pair excluded) the double-layer integrand on a sphere is
+    1 / (8 pi R r); the discrete sum is 1/2 minus the missing self-cell, which for a disc of
+    area a is sqrt(a / pi) / (4 R)."""
+    w, _, _ = oracle.gwn(fib.P, fib.N_true, fib.area, None, fib.P[:, :64])
+    pred = 0.5 - math.sqrt(fib.area[0] / math.pi) / 4.0
+    assert np.all(w < 0.5)
+    np.testing.assert_allclose(w, pred, atol=1e-3)
+
+
+@pytest.mark.parametrize("lam", [1.0, 10.0, 100.0])
+def test_screened_sphere_closed_form(fib, lam):
+    """Eq. 5 on a sphere of radius R = 1 (Yukawa double layer, x = s R, s = sqrt(lambda)):
+    inside w = (1+x) e^-x sinh(s rho)/(s rho), outside w = -e^(-s rho)(x cosh x - sinh x)/(s rho);
+    radial gradients C (s rho cosh(s rho) - sinh(s rho))/(s rho^2) with C = (1+x) e^-x and
+    (x cosh x - sinh x) e^(-s rho)(1 + s rho)/(s rho^2). The jump across the sphere is 1."""
+    Q = _sphere_q()[:, 1:]  # skip the centre (radial direction undefined)
+    w, g, _ = oracle.gwn(fib.P, fib.N_true, fib.area, None, Q, lam=lam)
+    s = math.sqrt(lam)
+    x = s
+    rho = np.linalg.norm(Q, axis=0)
+    C = (1 + x) * math.exp(-x)
+    w_in = C * np.sinh(s * rho) / (s * rho)
+    w_out = -np.exp(-s * rho) * (x * math.cosh(x) - math.sinh(x)) / (s * rho)
+    np.testing.assert_allclose(w, np.where(rho < 1, w_in, w_out), rtol=1e-5, atol=1e-6)
+    g_in = C * (s * rho * np.cosh(s * rho) - np.sinh(s * rho)) / (s * rho**2)
+    g_out = (x * math.cosh(x) - math.sinh(x)) * np.exp(-s * rho) * (1 + s * rho) / (s * rho**2)
+    radial = np.sum(g * Q, axis=0) / rho
+    np.testing.assert_allclose(radial, np.where(rho < 1, g_in, g_out), rtol=1e-4, atol=1e-6)
+    tang = np.linalg.norm(g - radial * Q / rho, axis=0)
+    assert tang.max() < 1e-4
+    # centre value
+    w0, _, _ = oracle.gwn(fib.P, fib.N_true, fib.area, None, np.zeros((3, 1)), lam=lam)
+    assert abs(w0[0] - C) < 1e-5 * max(1.0, C)
+
+
+def test_screened_jump_is_one(fib):
+    """The jump condition k = 1 (Sec. 4.2): w(R - t) - w(R + t) -> 1 as t -> 0."""
+    lam = 10.0
+    dirs = np.array([[0.3, -0.5, 0.81], [-0.7, 0.1, 0.2]]).T
+    dirs = dirs / np.linalg.norm(dirs, axis=0)
+    t = 0.25
+    w_i, _, _ = oracle.gwn(fib.P, fib.N_true, fib.area, None, dirs * (1 - t), lam=lam)
+    w_o, _, _ = oracle.gwn(fib.P, fib.N_true, fib.area, None, dirs * (1 + t), lam=lam)
+    s = math.sqrt(lam)
+    # closed-form jump of the two one-sided values at distance t, which tends to 1
+    C = (1 + s) * math.exp(-s)
+    pred = C * math.sinh(s * (1 - t)) / (s * (1 - t)) + math.exp(-s * (1 + t)) * (s * math.cosh(s) - math.sinh(s)) / (s * (1 + t))
+    np.testing.assert_allclose(w_i - w_o, pred, rtol=1e-5)
+    assert abs(C * math.sinh(s) / s + math.exp(-s) * (s * math.cosh(s) - math.sinh(s)) / s - 1.0) < 1e-12
+
+
+def _rand_cloud(rng, n=40):
+    P = rng.uniform(-1, 1, (3, n))
+    N = rng.standard_normal((3, n))
+    N /= np.linalg.norm(N, axis=0)
+    a = rng.uniform(0.01, 0.1, n)
+    d = rng.uniform(0.05, 0.4, n)
+    return P, N, a, d
+
+
+@pytest.mark.parametrize("lam", [0.0, 10.0])
+@pytest.mark.parametrize("use_delta", [False, True])
+def test_gradient_matches_finite_differences(lam, use_delta):
+    """grad w is the derivative of w with respect to the query (normals fixed, Sec. 4.1),
+    including the clamped branch and the s^2 term of the screened kernel."""
+    rng = np.random.default_rng(7)
+    P, N, a, d = _rand_cloud(rng)
+    D = d if use_delta else None
+    Q = rng.uniform(-1, 1, (3, 60))
+    h = 1e-5
+    w, g, fl = oracle.gwn(P, N, a, D, Q, lam=lam)
+    # keep queries away from the clamp boundary |r - delta_j| (finite differences straddle it)
+    r = np.linalg.norm(P[:, None, :] - Q[:, :, None], axis=0)  # [m, n]
+    ok = np.ones(Q.shape[1], bool)
+    if use_delta:
+        ok = np.min(np.abs(r - d[None, :]), axis=1) > 1e-3
+        assert np.any(np.min(r - d[None, :], axis=1) < 0), "no query exercises the clamped branch"
+    fd = np.zeros_like(g)
+    for k in range(3):
+        e = np.zeros((3, 1))
+        e[k] = h
+        wp, _, _ = oracle.gwn(P, N, a, D, Q + e, lam=lam, grad=False)
+        wm, _, _ = oracle.gwn(P, N, a, D, Q - e, lam=lam, grad=False)
+        fd[k] = (wp - wm) / (2 * h)
+    err = np.linalg.norm(g - fd, axis=0)[ok] / np.maximum(np.linalg.norm(g, axis=0)[ok], 1.0)
+    assert err.max() < 1e-5, err.max()
+
+
+def test_invariants():
+    """Linearity in a, odd in n, translation invariance, rotation equivariance and the
+    scaling law p -> alpha p, a -> alpha^2 a, delta -> alpha delta, lambda -> lambda/alpha^2:
+    w unchanged, grad w -> grad w / alpha."""
+    rng = np.random.default_rng(3)
+    P, N, a, d = _rand_cloud(rng, 50)
+    Q = rng.uniform(-1.2, 1.2, (3, 30))
+    lam = 7.0
+    w, g, _ = oracle.gwn(P, N, a, d, Q, lam=lam)
+    w2, g2, _ = oracle.gwn(P, N, 2.5 * a, d, Q, lam=lam)
+    np.testing.assert_allclose(w2, 2.5 * w, rtol=1e-12, atol=1e-14)
+    w3, g3, _ = oracle.gwn(P, -N, a, d, Q, lam=lam)
+    np.testing.assert_allclose(w3, -w, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(g3, -g, rtol=1e-12, atol=1e-12)
+    t = np.array([[0.3], [-1.1], [0.7]])
+    w4, g4, _ = oracle.gwn(P + t, N, a, d, Q + t, lam=lam)
+    np.testing.assert_allclose(w4, w, rtol=1e-9, atol=1e-10)
+    np.testing.assert_allclose(g4, g, rtol=1e-8, atol=1e-9)
+    Rm = np.linalg.qr(rng.standard_normal((3, 3)))[0]
+    w5, g5, _ = oracle.gwn(Rm @ P, Rm @ N, a, d, Rm @ Q, lam=lam)
+    np.testing.assert_allclose(w5, w, rtol=1e-9, atol=1e-10)
+    np.testing.assert_allclose(g5, Rm @ g, rtol=1e-8, atol=1e-9)
+    al = 1.7
+    w6, g6, _ = oracle.gwn(al * P, N, al * al * a, al * d, al * Q, lam=lam / al**2)
+    np.testing.assert_allclose(w6, w, rtol=1e-9, atol=1e-10)
+    np.testing.assert_allclose(g6, g / al, rtol=1e-8, atol=1e-9)
+
+
+def test_coincident_source_contributes_nothing():
+    """A query sitting exactly on a source gets nothing from it (self pair at an input point)."""
+    rng = np.random.default_rng(5)
+    P, N, a, d = _rand_cloud(rng, 30)
+    for lam, D in [(0.0, None), (10.0, d)]:
+        w, g, _ = oracle.gwn(P, N, a, D, P[:, :5], lam=lam)
+        for i in range(5):
+            keep = np.arange(30) != i
+            wi, gi, _ = oracle.gwn(P[:, keep], N[:, keep], a[keep], None if D is None else D[keep],
+                                   P[:, i:i + 1], lam=lam)
+            assert abs(wi[0] - w[i]) <= 1e-12 * max(1, abs(w[i]))
+            np.testing.assert_allclose(gi[:, 0], g[:, i], rtol=1e-12, atol=1e-12)
+
+
+def test_delta_zero_and_eps_floor():
+    """delta = 0 is the unmodified kernel; eps acts as a global floor on the radius."""
+    rng = np.random.default_rng(11)
+    P, N, a, d = _rand_cloud(rng, 30)
+    Q = rng.uniform(-1, 1, (3, 20))
+    w0, g0, _ = oracle.gwn(P, N, a, None, Q)
+    w1, g1, _ = oracle.gwn(P, N, a, np.zeros(30), Q)
+    np.testing.assert_array_equal(w0, w1)
+    np.testing.assert_array_equal(g0, g1)
+    w2, g2, _ = oracle.gwn(P, N, a, np.full(30, 0.2), Q)
+    w3, g3, _ = oracle.gwn(P, N, a, None, Q, eps=0.2)
+    np.testing.assert_array_equal(w2, w3)
+    np.testing.assert_array_equal(g2, g3)
+
+
+def test_update_and_stats():
+    """Eq. 7: unit normals anti-parallel to the gradient; zero gradient keeps the old normal.
+    The top-1% statistic equals the mean of the largest ceil(0.01 n) angles (numpy sort)."""
+    rng = np.random.default_rng(2)
+    n = 1000
+    g = rng.standard_normal((3, n))
+    g[:, 7] = 0.0
+    N0 = rng.standard_normal((3, n))
+    N0 /= np.linalg.norm(N0, axis=0)
+    N1, ch = oracle.update(g, N0)
+    np.testing.assert_allclose(np.linalg.norm(N1, axis=0), 1.0, rtol=1e-14)
+    keep = np.arange(n) != 7
+    cosang = np.sum(N1 * g, axis=0)[keep] / np.linalg.norm(g, axis=0)[keep]
+    np.testing.assert_allclose(cosang, -1.0, rtol=1e-14)
+    np.testing.assert_array_equal(N1[:, 7], N0[:, 7])
+    np.testing.assert_allclose(ch, np.linalg.norm(N1 - N0, axis=0), rtol=1e-14)
+    w = rng.standard_normal(n)
+    wm, top, mc = oracle.stats(w, ch, 0.01)
+    ang = np.degrees(np.arccos(np.clip(np.sum(N1 * N0, axis=0), -1, 1)))
+    k = math.ceil(0.01 * n)
+    assert oracle.top_count(n, 0.01) == k == 10
+    np.testing.assert_allclose(top, np.sort(ang)[::-1][:k].mean(), rtol=1e-9)
+    np.testing.assert_allclose(wm, w.mean(), rtol=1e-13)
+    np.testing.assert_allclose(mc, ch.mean(), rtol=1e-13)
+    assert oracle.top_count(1, 0.01) == 1 and oracle.top_count(150, 0.01) == 2
+
+
+def test_splitmix64_published_vector():
+    """SplitMix64 reference outputs for seed 1234567 (Vigna's splitmix64.c test vector)."""
+    want = [6457827717110365317, 3203168211198807973, 9817491932198370423, 4593380528125082431,
+            16408922859458223821]
+    assert [oracle.splitmix64(1234567, t) for t in range(5)] == want
+
+
+def test_random_normals_uniform_on_sphere():
+    n = 200_000
+    N = oracle.random_normals(42, n)
+    np.testing.assert_allclose(np.linalg.norm(N, axis=0), 1.0, rtol=1e-13)
+    tol = 5.0 / math.sqrt(n)
+    assert np.all(np.abs(N.mean(axis=1)) < tol)
+    np.testing.assert_allclose((N**2).mean(axis=1), 1 / 3, atol=tol)
+    assert np.abs(np.mean(N[0] * N[1])) < tol
+    assert not np.array_equal(N, oracle.random_normals(43, n))
+    np.testing.assert_array_equal(N[:, :100], oracle.random_normals(42, 100))
+
+
+def test_knn_against_kdtree():
+    from scipy.spatial import cKDTree
+    c = synth.torus_ellipsoids(3000, seed=5)
+    P = c.P.astype(np.float64)
+    idx, dist = oracle.knn_self(P, 10)
+    dd, ii = cKDTree(P.T).query(P.T, k=11)
+    np.testing.assert_allclose(dist, dd[:, 1:], rtol=1e-12, atol=1e-15)
+    np.testing.assert_array_equal(idx, ii[:, 1:])
+    delta = oracle.delta(P, 10)
+    np.testing.assert_allclose(delta, dd[:, 1:].mean(axis=1), rtol=1e-12)
+    R = P[:, ::7]
+    idx2, dist2 = oracle.knn(R, P, 16)
+    d3, i3 = cKDTree(R.T).query(P.T, k=16)
+    np.testing.assert_allclose(dist2, d3, rtol=1e-12, atol=1e-15)
+    np.testing.assert_array_equal(idx2, i3)
+
+
+@pytest.mark.slow
+def test_sphere_method_level():
+    """Sec. 4.1 and Eq. 4: exact outward normals are (nearly) a fixed point of the update, and
+    from random normals the iteration orients the sphere consistently (either global sign)."""
+    c = synth.sphere(1500, 0.005, seed=100)
+    P = c.P.astype(np.float64)
+    delta = oracle.delta(P, 10)
+    N1, st = oracle.dwg_run(P, c.area, delta, c.N_true, max_iters=1)
+    cos = np.sum(N1 * c.N_true, axis=0)
+    assert np.all(cos > 0)
+    assert np.degrees(np.arccos(np.clip(cos, -1, 1))).mean() < 10.0
+    N0 = oracle.random_normals(200, c.n)
+    NT, st = oracle.dwg_run(P, c.area, delta, N0, max_iters=40)
+    cos = np.sum(NT * c.N_true, axis=0)
+    agree = max(np.mean(cos > 0), np.mean(cos < 0))
+    assert agree >= 0.999, agree
