@@ -249,7 +249,9 @@ def test_sphere_method_level():
     from random normals the iteration orients the sphere consistently (either global sign)."""
     c = synth.sphere(1500, 0.005, seed=100)
     P = c.P.astype(np.float64)
-    delta = oracle.delta(P, 10)
+    # kernel radius: twice the mean distance to the 10 nearest points (the build's default
+    # reading of the modified Poisson kernel's threshold)
+    delta = 2.0 * oracle.delta(P, 10)
     N1, st = oracle.dwg_run(P, c.area, delta, c.N_true, max_iters=1)
     cos = np.sum(N1 * c.N_true, axis=0)
     assert np.all(cos > 0)
