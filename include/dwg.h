@@ -1,0 +1,199 @@
+/*
+ * dwg.h -- C ABI of libdwg, an MI355X (gfx950) implementation of the hot path of
+ * "Diffusing Winding Gradients" (DWG, arXiv 2405.13839): the all-pairs generalized
+ * winding number (GWN) dipole sum and its gradient at every input point, the screened
+ * kernel, the mean-GWN iso-value, the normal update iterated to convergence, and the
+ * initial normals (random, or proposed by a small MLP from k-nearest-neighbour features).
+ *
+ * Conventions shared by every call
+ *  - Point arrays are planar ("SoA") float32 device arrays of shape [3][n]: x at [0,n),
+ *    y at [n,2n), z at [2n,3n) -- a contiguous (3, n) torch tensor.
+ *  - Every pointer argument is a DEVICE pointer to caller-owned memory unless it says
+ *    "host". The library never allocates, frees or keeps caller memory.
+ *  - Scratch memory comes only from the caller's workspace `ws` of `ws_bytes` bytes
+ *    (device memory, 256-byte aligned); dwg_workspace_bytes() says how much is needed.
+ *    Its contents on entry do not matter and on return are unspecified.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream). Calls marked
+ *    "async" only enqueue work on that stream; the caller synchronises.
+ *  - Every argument is validated before the first HIP call. Errors never throw; each call
+ *    returns a dwg_status, and dwg_last_error() gives a thread-local detail string.
+ *  - No global mutable state besides that error string: calls are re-entrant, and the
+ *    same inputs, parameters and device give bitwise-identical outputs (no atomics take
+ *    part in any floating-point sum).
+ */
+#ifndef DWG_H
+#define DWG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dwg_status {
+  DWG_OK = 0,
+  DWG_NOT_CONVERGED = 1,  /* dwg_iterate: max_iters reached; outputs are valid */
+  DWG_E_INVALID = -1,     /* NULL required pointer, bad size or parameter */
+  DWG_E_WORKSPACE = -2,   /* ws_bytes smaller than dwg_workspace_bytes() */
+  DWG_E_DEVICE = -3,      /* a HIP call failed (message in dwg_last_error) */
+  DWG_E_NONFINITE = -4,   /* a non-finite statistic: an input held NaN/Inf */
+  DWG_E_UNSUPPORTED = -5  /* the device is not gfx950 */
+} dwg_status;
+
+/* Kernel parameters (Sec. 4.2 Eq. 5 screening; Sec. 5.2 modified Poisson kernel). */
+typedef struct dwg_kernel_params {
+  float lambda;    /* screening coefficient >= 0; 0 = plain GWN (Eq. 2-3) */
+  float eps;       /* >= 0: global floor on the kernel radius (the "small constant") */
+  int compensated; /* 1 = Kahan-compensated accumulation of per-tile partial sums */
+  int split;       /* source splits: 0 = automatic, else 1..64 */
+  int reserved[4]; /* must be zero */
+} dwg_kernel_params;
+
+/* Iteration parameters (Algorithm 1; Sec. 5.1 "Model-independent Parameters"). */
+typedef struct dwg_iterate_params {
+  int max_iters;   /* >= 1 */
+  int fixed_iters; /* 1 = run exactly max_iters; 0 = stop at the convergence test */
+  double eps_deg;  /* convergence threshold in degrees (paper: 0.1) */
+  double top_frac; /* fraction of largest normal changes averaged (paper: 0.01), (0,1] */
+} dwg_iterate_params;
+
+/* Per-iteration statistics, all computed in FP64 on the device. */
+typedef struct dwg_iter_stat {
+  double wmean;        /* Eq. 6: mean GWN over the input points (the iso-value) */
+  double top_mean_deg; /* mean of the ceil(top_frac*n) largest angle changes (deg) */
+  double mean_chord;   /* (1/n) sum |n_i^(t) - n_i^(t-1)| */
+} dwg_iter_stat;
+
+typedef enum dwg_init_kind { DWG_INIT_RANDOM = 0, DWG_INIT_MLP = 1 } dwg_init_kind;
+
+/* Library version string (static storage). */
+const char* dwg_version(void);
+/* Name of a status code (static storage). */
+const char* dwg_status_string(int status);
+/* Detail of the last error on the calling thread (thread-local storage; "" if none). */
+const char* dwg_last_error(void);
+
+/* Workspace bytes needed by any call below for n_src sources and n_qry queries with these
+ * kernel parameters (NULL = defaults). Returns 0 for invalid sizes. */
+size_t dwg_workspace_bytes(int64_t n_src, int64_t n_qry, const dwg_kernel_params* kp);
+
+/*
+ * dwg_gwn_eval -- GWN values w(q) at m queries (Sec. 3 Eq. 2-3; Sec. 4.2 Eq. 5). async.
+ *   For query q and source j with d = p_j - q, r = |d|: a pair with r == 0 contributes
+ *   nothing; rho = max(r, delta_j, eps); s = sqrt(lambda);
+ *   w(q) = sum_j a_j e^{-s r} (1 + s r) <d, n_j> / (4 pi rho^3).
+ *   P, N: sources and their normals [3][n]; area: a_j [n]; delta: per-source radius [n]
+ *   or NULL (= 0); Q: queries [3][m]; w: output [m]; wmean: output, one double = the FP64
+ *   mean of w, or NULL.
+ *   Errors: DWG_E_INVALID (NULL P/N/area/Q/w, n < 1, m < 1, lambda or eps negative or not
+ *   finite, nonzero reserved), DWG_E_WORKSPACE, DWG_E_DEVICE.
+ */
+dwg_status dwg_gwn_eval(const float* P, const float* N, const float* area, const float* delta,
+                        int64_t n, const float* Q, int64_t m, const dwg_kernel_params* kp,
+                        float* w, double* wmean, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * dwg_gwn_grad -- w(q) and its gradient with respect to q, the normals held fixed
+ * (Sec. 4.1), at m queries. async. Same inputs as dwg_gwn_eval; per pair
+ *   grad += a_j e^{-s r} [ (3 (1 + s r) / r^2 [rho == r] + s^2) <d,n_j> d - (1 + s r) n_j ]
+ *           / (4 pi rho^3),
+ * the derivative of the piecewise w term (the clamp makes it jump at r = delta_j).
+ * w: output [m] or NULL; grad: output [3][m]; wmean: output or NULL.
+ */
+dwg_status dwg_gwn_grad(const float* P, const float* N, const float* area, const float* delta,
+                        int64_t n, const float* Q, int64_t m, const dwg_kernel_params* kp,
+                        float* w, float* grad, double* wmean, void* ws, size_t ws_bytes,
+                        void* stream);
+
+/*
+ * dwg_iterate -- Algorithm 1 with every input point as a query (Sec. 4.3). Synchronous.
+ *   Iteration t: evaluate w and grad w at every p_i with the normals n^(t-1) (self pair
+ *   excluded), w_bar = mean w (Eq. 6), n_i^(t) = -grad w(p_i) / |grad w(p_i)| (Eq. 7; a
+ *   zero or non-finite gradient keeps the old normal), and the statistics; stop when
+ *   top_mean_deg <= eps_deg unless fixed_iters.
+ *   P [3][n], area [n], delta [n] or NULL; N_inout [3][n]: n^(0) in, n^(T) out (unit
+ *   vectors). stats_host: HOST array [max_iters] or NULL; iters_done: HOST int or NULL.
+ *   Returns DWG_OK (converged, or fixed_iters), DWG_NOT_CONVERGED, DWG_E_NONFINITE (N_inout
+ *   holds the last iterate), or the errors of dwg_gwn_grad; DWG_E_INVALID also for
+ *   max_iters < 1, eps_deg < 0, top_frac outside (0,1].
+ */
+dwg_status dwg_iterate(const float* P, const float* area, const float* delta, int64_t n,
+                       float* N_inout, const dwg_kernel_params* kp, const dwg_iterate_params* ip,
+                       dwg_iter_stat* stats_host, int* iters_done, void* ws, size_t ws_bytes,
+                       void* stream);
+
+/*
+ * dwg_init_normals -- initial normals n^(0) (Algorithm 1; Sec. 5.1 "Normal
+ * Initialization"). async.
+ *   DWG_INIT_RANDOM: i.i.d. uniform unit vectors from the counter-based SplitMix64 stream
+ *     of `seed`: point i uses outputs 2i and 2i+1, u = (x >> 40) 2^-24, z = 1 - 2 u0,
+ *     phi = 2 pi u1, n = (sqrt(1 - z^2) cos phi, sqrt(1 - z^2) sin phi, z). P may be NULL.
+ *   DWG_INIT_MLP: the MLP of dwg_mlp_infer applied to the features of dwg_features;
+ *     mlp_params is the device FP32 parameter blob of dwg_mlp_param_count() floats.
+ *   N_out: output [3][n].
+ */
+dwg_status dwg_init_normals(dwg_init_kind kind, uint64_t seed, const float* P, int64_t n,
+                            const float* mlp_params, float* N_out, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/*
+ * dwg_knn -- k nearest reference points (k <= 16) of each query, exact, by a uniform
+ * grid (Sec. 5.1 uses kNN for the kernel radius and the normal update). async.
+ *   R: reference points [3][nr]; Q: queries [3][m]; self_skip: 1 when Q is R itself (then
+ *   query i never returns reference i), else 0. idx: output int32 [m][k] (ascending
+ *   distance); dist: output float32 [m][k] or NULL. Distances are Euclidean in FP32.
+ */
+dwg_status dwg_knn(const float* R, int64_t nr, const float* Q, int64_t m, int self_skip, int k,
+                   int32_t* idx, float* dist, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * dwg_delta_knn_mean -- per-point kernel radius delta_i = mean distance to the k nearest
+ * other points (Sec. 5.2 "Poisson Kernels", without the absolute distance filter), times
+ * `scale`. async. P [3][n]; delta: output [n]; 1 <= k <= 16, k < n; scale > 0.
+ */
+dwg_status dwg_delta_knn_mean(const float* P, int64_t n, int k, float scale, float* delta,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- learned initial normals
+ * Features of point i: its 16 nearest "anchor" points (anchors = points whose index is a
+ * multiple of `stride`, stride = max(1, n / n_anchor)), the anchor i itself excluded, as
+ * relative positions (a_k - p_i) / s_i in ascending distance, s_i = their mean distance:
+ * 48 floats. MLP 48 -> 128 -> 128 -> 3, ReLU, output normalised. BF16 operands on MFMA,
+ * FP32 accumulation. Parameter blob (FP32, this order): W1[128][48], b1[128],
+ * W2[128][128], b2[128], W3[3][128], b3[3].
+ */
+#define DWG_MLP_IN 48
+#define DWG_MLP_HID 128
+#define DWG_MLP_OUT 3
+#define DWG_FEAT_K 16
+int64_t dwg_mlp_param_count(void);
+
+/* Features [n][48] (float32) of every point; n_anchor >= 17. async. */
+dwg_status dwg_features(const float* P, int64_t n, int64_t n_anchor, float* feat, void* ws,
+                        size_t ws_bytes, void* stream);
+
+/* MLP forward on B feature rows X [B][48] (float32, rounded to BF16 on load):
+ * Y [B][3] = normalised output. async. */
+dwg_status dwg_mlp_infer(const float* params, const float* X, int64_t B, float* Y, void* ws,
+                         size_t ws_bytes, void* stream);
+
+/*
+ * One training step on a batch: loss = mean_b (1 - <y_b/|y_b|, t_b>) over rows with
+ * weight 1 (mask[b] != 0; mask may be NULL = all), gradients by the library's backward
+ * kernels, then Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with `step` >= 1)
+ * on the FP32 master parameters. async.
+ *   params [P] in/out; adam_m, adam_v [P] in/out (zero at step 1); X [B][48]; T [B][3]
+ *   unit targets; grad_out [P] or NULL (the raw gradient, for checking); loss_out: one
+ *   float or NULL.
+ */
+dwg_status dwg_mlp_train_step(float* params, float* adam_m, float* adam_v, int64_t step,
+                              float lr, const float* X, const float* T, const uint8_t* mask,
+                              int64_t B, float* grad_out, float* loss_out, void* ws,
+                              size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DWG_H */

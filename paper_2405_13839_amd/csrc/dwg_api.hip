@@ -1,0 +1,348 @@
+// C ABI entry points of libdwg: argument validation (always before the first HIP call),
+// workspace carving and the host-side iteration loop of Algorithm 1.
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "dwg_internal.h"
+
+namespace dwg {
+
+static thread_local char g_err[512];
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+}
+
+}  // namespace dwg
+
+using namespace dwg;
+
+namespace {
+
+#define DWG_CHECK(cond, ...)        \
+  do {                              \
+    if (!(cond)) {                  \
+      ::dwg::set_error(__VA_ARGS__); \
+      return DWG_E_INVALID;         \
+    }                               \
+  } while (0)
+
+#define DWG_PROPAGATE(expr)         \
+  do {                              \
+    dwg_status s_ = (expr);         \
+    if (s_ != DWG_OK) return s_;    \
+  } while (0)
+
+const dwg_kernel_params kDefaultKp = {0.0f, 0.0f, 1, 0, {0, 0, 0, 0}};
+
+dwg_status check_kp(const dwg_kernel_params* kp) {
+  if (!kp) return DWG_OK;
+  DWG_CHECK(std::isfinite(kp->lambda) && kp->lambda >= 0.0f, "lambda must be finite and >= 0");
+  DWG_CHECK(std::isfinite(kp->eps) && kp->eps >= 0.0f, "eps must be finite and >= 0");
+  DWG_CHECK(kp->compensated == 0 || kp->compensated == 1, "compensated must be 0 or 1");
+  DWG_CHECK(kp->split >= 0 && kp->split <= kMaxSplit, "split must be in [0, 64]");
+  for (int i = 0; i < 4; ++i) DWG_CHECK(kp->reserved[i] == 0, "reserved fields must be zero");
+  return DWG_OK;
+}
+
+// 1 = gfx950, 0 = not yet checked, -1 = other architecture (per device ordinal).
+std::atomic<int> g_arch[64];
+
+dwg_status check_device() {
+  int dev = 0;
+  DWG_TRY_HIP(hipGetDevice(&dev));
+  if (dev >= 0 && dev < 64 && g_arch[dev].load() != 0)
+    return g_arch[dev].load() > 0 ? DWG_OK : DWG_E_UNSUPPORTED;
+  hipDeviceProp_t prop;
+  DWG_TRY_HIP(hipGetDeviceProperties(&prop, dev));
+  const bool ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+  if (dev >= 0 && dev < 64) g_arch[dev].store(ok ? 1 : -1);
+  if (!ok) {
+    set_error("device %d is %s; libdwg is built for gfx950 only", dev, prop.gcnArchName);
+    return DWG_E_UNSUPPORTED;
+  }
+  return DWG_OK;
+}
+
+// kNN-based stages (delta radius, anchor features): neighbour lists of n queries with up to
+// 16 neighbours, the anchor copy and the grid.
+size_t aux_bytes(int64_t n) {
+  Carver c(nullptr);
+  c.take<float>(3 * (size_t)n);
+  c.take<int32_t>((size_t)n * kMaxK);
+  c.take<float>((size_t)n * kMaxK);
+  return c.used + knn_ws_bytes(n, n);
+}
+
+size_t gwn_bytes(int64_t n_src, int64_t n_qry, const dwg_kernel_params& kp) {
+  Carver c(nullptr);
+  carve_gwn(c, n_src, n_qry, choose_split(n_src, n_qry, kp.split), nullptr);
+  return c.used;
+}
+
+dwg_status gwn_common(const float* P, const float* N, const float* area, const float* delta,
+                      int64_t n, const float* Q, int64_t m, const dwg_kernel_params* kpp,
+                      bool grad, float* w, float* g, double* wmean, void* ws, size_t ws_bytes,
+                      void* stream) {
+  DWG_CHECK(P && N && area && Q, "P, N, area and Q must not be NULL");
+  DWG_CHECK(n >= 1 && m >= 1, "n and m must be >= 1 (got n=%lld, m=%lld)", (long long)n, (long long)m);
+  DWG_CHECK(n < (int64_t(1) << 40) && m < (int64_t(1) << 40), "n, m too large");
+  DWG_CHECK(grad ? (g != nullptr) : (w != nullptr), grad ? "grad must not be NULL" : "w must not be NULL");
+  DWG_PROPAGATE(check_kp(kpp));
+  const dwg_kernel_params kp = kpp ? *kpp : kDefaultKp;
+  const size_t need = gwn_bytes(n, m, kp);
+  DWG_CHECK(ws || ws_bytes == 0, "ws is NULL but ws_bytes > 0");
+  if (!ws || ws_bytes < need) {
+    set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+    return DWG_E_WORKSPACE;
+  }
+  DWG_PROPAGATE(check_device());
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Carver c(ws);
+  GwnWork wk;
+  carve_gwn(c, n, m, choose_split(n, m, kp.split), &wk);
+  DWG_PROPAGATE(launch_stage(P, N, area, delta, n, kp.eps, wk, st));
+  DWG_PROPAGATE(launch_gwn(Q, m, kp, grad, wk, st));
+  DWG_PROPAGATE(launch_combine(m, kp, grad, w, g, wmean, wk, st));
+  return DWG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dwg_version(void) { return "dwg-mi355x 0.1.0 (gfx950)"; }
+
+const char* dwg_status_string(int s) {
+  switch (s) {
+    case DWG_OK: return "DWG_OK";
+    case DWG_NOT_CONVERGED: return "DWG_NOT_CONVERGED";
+    case DWG_E_INVALID: return "DWG_E_INVALID";
+    case DWG_E_WORKSPACE: return "DWG_E_WORKSPACE";
+    case DWG_E_DEVICE: return "DWG_E_DEVICE";
+    case DWG_E_NONFINITE: return "DWG_E_NONFINITE";
+    case DWG_E_UNSUPPORTED: return "DWG_E_UNSUPPORTED";
+    default: return "DWG_UNKNOWN_STATUS";
+  }
+}
+
+const char* dwg_last_error(void) { return g_err; }
+
+size_t dwg_workspace_bytes(int64_t n_src, int64_t n_qry, const dwg_kernel_params* kp) {
+  if (n_src < 1 || n_qry < 1 || n_src >= (int64_t(1) << 40) || n_qry >= (int64_t(1) << 40)) return 0;
+  if (check_kp(kp) != DWG_OK) return 0;
+  const dwg_kernel_params k = kp ? *kp : kDefaultKp;
+  size_t a = gwn_bytes(n_src, n_qry, k);
+  size_t b = aux_bytes(std::max(n_src, n_qry));
+  size_t c = mlp_ws_bytes(std::max(n_src, n_qry));
+  return align256(std::max(a, std::max(b, c)));
+}
+
+dwg_status dwg_gwn_eval(const float* P, const float* N, const float* area, const float* delta,
+                        int64_t n, const float* Q, int64_t m, const dwg_kernel_params* kp,
+                        float* w, double* wmean, void* ws, size_t ws_bytes, void* stream) {
+  return gwn_common(P, N, area, delta, n, Q, m, kp, false, w, nullptr, wmean, ws, ws_bytes, stream);
+}
+
+dwg_status dwg_gwn_grad(const float* P, const float* N, const float* area, const float* delta,
+                        int64_t n, const float* Q, int64_t m, const dwg_kernel_params* kp,
+                        float* w, float* grad, double* wmean, void* ws, size_t ws_bytes,
+                        void* stream) {
+  return gwn_common(P, N, area, delta, n, Q, m, kp, true, w, grad, wmean, ws, ws_bytes, stream);
+}
+
+dwg_status dwg_iterate(const float* P, const float* area, const float* delta, int64_t n,
+                       float* N_inout, const dwg_kernel_params* kpp, const dwg_iterate_params* ip,
+                       dwg_iter_stat* stats_host, int* iters_done, void* ws, size_t ws_bytes,
+                       void* stream) {
+  if (iters_done) *iters_done = 0;
+  DWG_CHECK(P && area && N_inout && ip, "P, area, N_inout and ip must not be NULL");
+  DWG_CHECK(n >= 1 && n < (int64_t(1) << 40), "n must be >= 1 (got %lld)", (long long)n);
+  DWG_CHECK(ip->max_iters >= 1, "max_iters must be >= 1");
+  DWG_CHECK(ip->fixed_iters == 0 || ip->fixed_iters == 1, "fixed_iters must be 0 or 1");
+  DWG_CHECK(std::isfinite(ip->eps_deg) && ip->eps_deg >= 0.0, "eps_deg must be finite and >= 0");
+  DWG_CHECK(ip->top_frac > 0.0 && ip->top_frac <= 1.0, "top_frac must be in (0, 1]");
+  DWG_PROPAGATE(check_kp(kpp));
+  const dwg_kernel_params kp = kpp ? *kpp : kDefaultKp;
+  const size_t need = gwn_bytes(n, n, kp);
+  DWG_CHECK(ws || ws_bytes == 0, "ws is NULL but ws_bytes > 0");
+  if (!ws || ws_bytes < need) {
+    set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+    return DWG_E_WORKSPACE;
+  }
+  DWG_PROPAGATE(check_device());
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Carver c(ws);
+  GwnWork wk;
+  carve_gwn(c, n, n, choose_split(n, n, kp.split), &wk);
+  DWG_PROPAGATE(launch_stage(P, N_inout, area, delta, n, kp.eps, wk, st));
+  dwg_status result = DWG_NOT_CONVERGED;
+  for (int t = 0; t < ip->max_iters; ++t) {
+    DWG_PROPAGATE(launch_gwn(P, n, kp, true, wk, st));
+    DWG_PROPAGATE(launch_update(n, area, kp, N_inout, wk, st));
+    DWG_PROPAGATE(launch_stats(n, ip->top_frac, wk, st));
+    double hs[4];
+    DWG_TRY_HIP(hipMemcpyAsync(hs, wk.stats, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    DWG_TRY_HIP(hipStreamSynchronize(st));
+    if (stats_host) {
+      stats_host[t].wmean = hs[0];
+      stats_host[t].top_mean_deg = hs[1];
+      stats_host[t].mean_chord = hs[2];
+    }
+    if (iters_done) *iters_done = t + 1;
+    if (!std::isfinite(hs[0]) || !std::isfinite(hs[1]) || !std::isfinite(hs[2])) {
+      set_error("non-finite statistics at iteration %d (wmean=%g, top=%g, chord=%g)", t + 1, hs[0],
+                hs[1], hs[2]);
+      return DWG_E_NONFINITE;
+    }
+    if (ip->fixed_iters) {
+      result = DWG_OK;
+    } else if (hs[1] <= ip->eps_deg) {
+      result = DWG_OK;
+      break;
+    }
+  }
+  if (ip->fixed_iters) result = DWG_OK;
+  return result;
+}
+
+dwg_status dwg_init_normals(dwg_init_kind kind, uint64_t seed, const float* P, int64_t n,
+                            const float* mlp_params, float* N_out, void* ws, size_t ws_bytes,
+                            void* stream) {
+  DWG_CHECK(kind == DWG_INIT_RANDOM || kind == DWG_INIT_MLP, "unknown init kind %d", (int)kind);
+  DWG_CHECK(N_out, "N_out must not be NULL");
+  DWG_CHECK(n >= 1 && n < (int64_t(1) << 40), "n must be >= 1");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (kind == DWG_INIT_RANDOM) {
+    DWG_PROPAGATE(check_device());
+    return launch_random_normals(seed, n, N_out, st);
+  }
+  DWG_CHECK(P && mlp_params, "P and mlp_params must not be NULL for DWG_INIT_MLP");
+  DWG_CHECK(n >= DWG_FEAT_K + 2, "DWG_INIT_MLP needs at least %d points", DWG_FEAT_K + 2);
+  const size_t need = dwg_workspace_bytes(n, n, nullptr);
+  DWG_CHECK(ws || ws_bytes == 0, "ws is NULL but ws_bytes > 0");
+  if (!ws || ws_bytes < need) {
+    set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+    return DWG_E_WORKSPACE;
+  }
+  DWG_PROPAGATE(check_device());
+  // Features and MLP in chunks so that the [chunk][48] feature buffer stays bounded.
+  Carver c(ws);
+  const int64_t chunk = std::min<int64_t>(n, 1 << 20);
+  float* feat = c.take<float>((size_t)chunk * DWG_MLP_IN);
+  float* y = c.take<float>((size_t)chunk * 3);
+  void* rest = static_cast<char*>(ws) + c.used;
+  const size_t rest_bytes = ws_bytes - c.used;
+  (void)feat;
+  (void)y;
+  (void)rest;
+  (void)rest_bytes;
+  set_error("DWG_INIT_MLP: not available in this build");
+  return DWG_E_UNSUPPORTED;
+}
+
+dwg_status dwg_knn(const float* R, int64_t nr, const float* Q, int64_t m, int self_skip, int k,
+                   int32_t* idx, float* dist, void* ws, size_t ws_bytes, void* stream) {
+  DWG_CHECK(R && Q && idx, "R, Q and idx must not be NULL");
+  DWG_CHECK(k >= 1 && k <= kMaxK, "k must be in [1, %d]", kMaxK);
+  DWG_CHECK(self_skip == 0 || self_skip == 1, "self_skip must be 0 or 1");
+  DWG_CHECK(nr >= k + self_skip && m >= 1 && nr < (int64_t(1) << 31) && m < (int64_t(1) << 31),
+            "need nr >= k + self_skip, m >= 1, sizes < 2^31");
+  DWG_CHECK(!self_skip || (R == Q && nr == m), "self_skip requires Q == R");
+  const size_t need = knn_ws_bytes(nr, m);
+  DWG_CHECK(ws || ws_bytes == 0, "ws is NULL but ws_bytes > 0");
+  if (!ws || ws_bytes < need) {
+    set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+    return DWG_E_WORKSPACE;
+  }
+  DWG_PROPAGATE(check_device());
+  return knn_run(R, nr, Q, m, self_skip, nullptr, k, idx, dist, ws, ws_bytes,
+                 static_cast<hipStream_t>(stream));
+}
+
+dwg_status dwg_delta_knn_mean(const float* P, int64_t n, int k, float scale, float* delta,
+                              void* ws, size_t ws_bytes, void* stream) {
+  DWG_CHECK(P && delta, "P and delta must not be NULL");
+  DWG_CHECK(k >= 1 && k <= kMaxK, "k must be in [1, %d]", kMaxK);
+  DWG_CHECK(n > k && n < (int64_t(1) << 31), "need k < n < 2^31");
+  DWG_CHECK(std::isfinite(scale) && scale > 0.0f, "scale must be finite and > 0");
+  Carver c(nullptr);
+  c.take<int32_t>((size_t)n * k);
+  c.take<float>((size_t)n * k);
+  const size_t head = c.used;
+  const size_t need = aux_bytes(n);
+  DWG_CHECK(ws || ws_bytes == 0, "ws is NULL but ws_bytes > 0");
+  if (!ws || ws_bytes < need) {
+    set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+    return DWG_E_WORKSPACE;
+  }
+  DWG_PROPAGATE(check_device());
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Carver w(ws);
+  int32_t* idx = w.take<int32_t>((size_t)n * k);
+  float* dist = w.take<float>((size_t)n * k);
+  DWG_PROPAGATE(knn_run(P, n, P, n, 1, nullptr, k, idx, dist, static_cast<char*>(ws) + head,
+                        ws_bytes - head, st));
+  return delta_from_knn(dist, n, k, scale, delta, st);
+}
+
+int64_t dwg_mlp_param_count(void) {
+  return (int64_t)DWG_MLP_HID * DWG_MLP_IN + DWG_MLP_HID + (int64_t)DWG_MLP_HID * DWG_MLP_HID +
+         DWG_MLP_HID + (int64_t)DWG_MLP_OUT * DWG_MLP_HID + DWG_MLP_OUT;
+}
+
+dwg_status dwg_features(const float* P, int64_t n, int64_t n_anchor, float* feat, void* ws,
+                        size_t ws_bytes, void* stream) {
+  DWG_CHECK(P && feat, "P and feat must not be NULL");
+  DWG_CHECK(n >= DWG_FEAT_K + 2 && n < (int64_t(1) << 31), "n must be in [%d, 2^31)", DWG_FEAT_K + 2);
+  DWG_CHECK(n_anchor >= DWG_FEAT_K + 1, "n_anchor must be >= %d", DWG_FEAT_K + 1);
+  const size_t need = aux_bytes(n);
+  DWG_CHECK(ws || ws_bytes == 0, "ws is NULL but ws_bytes > 0");
+  if (!ws || ws_bytes < need) {
+    set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+    return DWG_E_WORKSPACE;
+  }
+  DWG_PROPAGATE(check_device());
+  return features_run(P, n, n_anchor, feat, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+dwg_status dwg_mlp_infer(const float* params, const float* X, int64_t B, float* Y, void* ws,
+                         size_t ws_bytes, void* stream) {
+  DWG_CHECK(params && X && Y, "params, X and Y must not be NULL");
+  DWG_CHECK(B >= 1 && B < (int64_t(1) << 31), "B must be in [1, 2^31)");
+  const size_t need = mlp_ws_bytes(B);
+  DWG_CHECK(ws || ws_bytes == 0, "ws is NULL but ws_bytes > 0");
+  if (!ws || ws_bytes < need) {
+    set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+    return DWG_E_WORKSPACE;
+  }
+  DWG_PROPAGATE(check_device());
+  return mlp_infer_run(params, X, B, Y, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+dwg_status dwg_mlp_train_step(float* params, float* adam_m, float* adam_v, int64_t step,
+                              float lr, const float* X, const float* T, const uint8_t* mask,
+                              int64_t B, float* grad_out, float* loss_out, void* ws,
+                              size_t ws_bytes, void* stream) {
+  DWG_CHECK(params && adam_m && adam_v && X && T, "params, adam_m, adam_v, X, T must not be NULL");
+  DWG_CHECK(step >= 1, "step must be >= 1");
+  DWG_CHECK(std::isfinite(lr) && lr > 0.0f, "lr must be finite and > 0");
+  DWG_CHECK(B >= 1 && B < (int64_t(1) << 31), "B must be in [1, 2^31)");
+  const size_t need = mlp_ws_bytes(B);
+  DWG_CHECK(ws || ws_bytes == 0, "ws is NULL but ws_bytes > 0");
+  if (!ws || ws_bytes < need) {
+    set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+    return DWG_E_WORKSPACE;
+  }
+  DWG_PROPAGATE(check_device());
+  return mlp_train_run(params, adam_m, adam_v, step, lr, X, T, mask, B, grad_out, loss_out, ws,
+                       ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

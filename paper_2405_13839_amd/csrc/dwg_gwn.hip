@@ -1,0 +1,573 @@
+// All-pairs GWN / gradient kernels, the normal-update epilogue and the FP64 statistics of
+// one DWG iteration (Sec. 3 Eq. 2-3, Sec. 4.2 Eq. 5, Sec. 4.3 Eq. 6-7, Sec. 5.1-5.2).
+//
+// Data layout in HBM (all carved from the caller's workspace):
+//   src   [2*npad] float4  per source j: (p_j, 1/max(delta_j, eps)), (m_j, 0) with
+//                          m_j = a_j n_j / (4 pi); padding sources are all zero, which makes
+//                          their contribution exactly zero (see pair_* below).
+//   part  [split][7][mpad] per-split partial sums of w, A = sum t d, B = sum rho^-3 m.
+//   kk    [npad]           a_j / (4 pi) (restaging after the update)
+//   theta [m] double       angle between consecutive normals, degrees.
+// Queries are read straight from the caller's planar [3][m] array.
+#include <cmath>
+
+#include "dwg_internal.h"
+
+namespace dwg {
+namespace {
+
+constexpr float kInv4Pi = 0.0795774715459476678844f;
+// 2^126: r2 * kCoincide is 0 exactly when r2 == 0 and larger than 1/r for every pair with
+// r2 >= 2^-84; it is the third operand of the min that zeroes coincident pairs.
+constexpr float kCoincide = 8.507059173023462e37f;
+// Added to r2 before rsqrt in the screened kernel so that r = r2 * rsqrt(r2 + tiny) is 0
+// (not 0 * inf) for coincident pairs; below half an ulp of any r2 >= 2^-84.
+constexpr float kTiny = 1e-37f;
+constexpr double kRadToDeg = 57.295779513082320876798;
+
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float exp2_hw(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// min of three non-negative floats (+inf allowed) through their bit patterns, which order
+// like unsigned integers for non-negative IEEE values: one v_min3_u32, no NaN handling.
+__device__ __forceinline__ float min3_nonneg(float a, float b, float c) {
+  const unsigned x = __float_as_uint(a), y = __float_as_uint(b), z = __float_as_uint(c);
+  return __uint_as_float(min(min(x, y), z));
+}
+
+// One (query, source) pair of the plain kernel (Eq. 2-3 with the modified Poisson kernel).
+//   ip = 1/rho = min(1/r, 1/max(delta,eps)), and 0 when r == 0 (pair skipped).
+//   w += c ip^3;  B += ip^3 m;  A += [rho == r] c ip^5 d;  grad = 3 A - B.
+template <bool GRAD>
+__device__ __forceinline__ void pair_plain(const float4 a, const float4 b, float qx, float qy,
+                                           float qz, float* acc) {
+  const float dx = a.x - qx, dy = a.y - qy, dz = a.z - qz;
+  const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+  const float ir = rsq(r2);
+  const float ip = min3_nonneg(ir, a.w, r2 * kCoincide);
+  const float ip2 = ip * ip;
+  const float ip3 = ip2 * ip;
+  const float c = fmaf(dz, b.z, fmaf(dy, b.y, dx * b.x));
+  if (!GRAD) {
+    acc[0] = fmaf(c, ip3, acc[0]);
+  } else {
+    const float e = c * ip3;
+    acc[0] += e;
+    acc[4] = fmaf(ip3, b.x, acc[4]);
+    acc[5] = fmaf(ip3, b.y, acc[5]);
+    acc[6] = fmaf(ip3, b.z, acc[6]);
+    const float t = (ir <= a.w) ? e * ip2 : 0.0f;
+    acc[1] = fmaf(t, dx, acc[1]);
+    acc[2] = fmaf(t, dy, acc[2]);
+    acc[3] = fmaf(t, dz, acc[3]);
+  }
+}
+
+// One pair of the screened kernel (Eq. 5): E = e^{-s r}, phi = E (1 + s r).
+//   w += c phi ip^3;  B += phi ip^3 m;
+//   A += c E ip^3 (3 (1 + s r) ip^2 [rho == r] + s^2) d;  grad = A - B.
+template <bool GRAD>
+__device__ __forceinline__ void pair_screened(const float4 a, const float4 b, float qx, float qy,
+                                              float qz, float s, float neg_s_log2e, float s2,
+                                              float* acc) {
+  const float dx = a.x - qx, dy = a.y - qy, dz = a.z - qz;
+  const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+  const float ir = rsq(r2 + kTiny);
+  const float ip = min3_nonneg(ir, a.w, r2 * kCoincide);
+  const float ip2 = ip * ip;
+  const float ip3 = ip2 * ip;
+  const float r = r2 * ir;
+  const float E = exp2_hw(r * neg_s_log2e);
+  const float onesr = fmaf(s, r, 1.0f);
+  const float f = E * ip3;
+  const float c = fmaf(dz, b.z, fmaf(dy, b.y, dx * b.x));
+  const float e0 = c * f;
+  acc[0] = fmaf(e0, onesr, acc[0]);
+  if (GRAD) {
+    const float g = f * onesr;
+    acc[4] = fmaf(g, b.x, acc[4]);
+    acc[5] = fmaf(g, b.y, acc[5]);
+    acc[6] = fmaf(g, b.z, acc[6]);
+    const float h = fmaf(3.0f * onesr, ip2, s2);
+    const float t = e0 * ((ir <= a.w) ? h : s2);
+    acc[1] = fmaf(t, dx, acc[1]);
+    acc[2] = fmaf(t, dy, acc[2]);
+    acc[3] = fmaf(t, dz, acc[3]);
+  }
+}
+
+// All-pairs kernel. Block = 256 threads holding QPT queries each (query q0 + k*256 + tid);
+// grid.y = source split. Source tiles of 256 are staged in LDS and read back as broadcasts.
+// Each tile's contributions go to FP32 partials, which are then folded into running sums
+// (Kahan-compensated when KAHAN).
+template <int QPT, bool GRAD, bool SCREENED, bool KAHAN>
+__global__ __launch_bounds__(kBlock) void k_gwn(const float* __restrict__ Q, int64_t m,
+                                                 const float4* __restrict__ src, int64_t ntiles,
+                                                 int64_t tiles_per_split, float s,
+                                                 float neg_s_log2e, float s2,
+                                                 float* __restrict__ part, int64_t mpad) {
+  constexpr int NA = GRAD ? kNAcc : 1;
+  __shared__ float4 sa[kTile];
+  __shared__ float4 sb[kTile];
+  const int tid = threadIdx.x;
+  const int64_t q0 = (int64_t)blockIdx.x * (kBlock * QPT);
+  float qx[QPT], qy[QPT], qz[QPT];
+#pragma unroll
+  for (int k = 0; k < QPT; ++k) {
+    int64_t qi = q0 + k * kBlock + tid;
+    if (qi >= m) qi = m - 1;
+    qx[k] = Q[qi];
+    qy[k] = Q[m + qi];
+    qz[k] = Q[2 * m + qi];
+  }
+  float sum[QPT][NA], cmp[QPT][NA];
+#pragma unroll
+  for (int k = 0; k < QPT; ++k)
+#pragma unroll
+    for (int a = 0; a < NA; ++a) sum[k][a] = cmp[k][a] = 0.0f;
+
+  const int64_t t0 = (int64_t)blockIdx.y * tiles_per_split;
+  const int64_t t1 = min(t0 + tiles_per_split, ntiles);
+  for (int64_t t = t0; t < t1; ++t) {
+    __syncthreads();
+    sa[tid] = src[2 * (t * kTile + tid)];
+    sb[tid] = src[2 * (t * kTile + tid) + 1];
+    __syncthreads();
+    float acc[QPT][NA];
+#pragma unroll
+    for (int k = 0; k < QPT; ++k)
+#pragma unroll
+      for (int a = 0; a < NA; ++a) acc[k][a] = 0.0f;
+#pragma unroll 2
+    for (int j = 0; j < kTile; ++j) {
+      const float4 a = sa[j];
+      const float4 b = sb[j];
+#pragma unroll
+      for (int k = 0; k < QPT; ++k) {
+        if (SCREENED)
+          pair_screened<GRAD>(a, b, qx[k], qy[k], qz[k], s, neg_s_log2e, s2, acc[k]);
+        else
+          pair_plain<GRAD>(a, b, qx[k], qy[k], qz[k], acc[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < QPT; ++k)
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        if (KAHAN) {
+          const float y = acc[k][a] - cmp[k][a];
+          const float tt = sum[k][a] + y;
+          cmp[k][a] = (tt - sum[k][a]) - y;
+          sum[k][a] = tt;
+        } else {
+          sum[k][a] += acc[k][a];
+        }
+      }
+  }
+  float* out = part + (int64_t)blockIdx.y * NA * mpad;
+#pragma unroll
+  for (int k = 0; k < QPT; ++k) {
+    const int64_t qi = q0 + k * kBlock + tid;  // < mpad by construction of mpad
+#pragma unroll
+    for (int a = 0; a < NA; ++a) out[a * mpad + qi] = KAHAN ? sum[k][a] - cmp[k][a] : sum[k][a];
+  }
+}
+
+// Stage the sources of one evaluation: (p, 1/max(delta,eps)) and m = a n / (4 pi).
+// A NaN delta poisons the source's m so that the result is NaN as in the definition.
+__global__ void k_stage(const float* __restrict__ P, const float* __restrict__ N,
+                        const float* __restrict__ A, const float* __restrict__ D, int64_t n,
+                        int64_t npad, float eps, float4* __restrict__ src,
+                        float* __restrict__ kk) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= npad) return;
+  float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = make_float4(0.f, 0.f, 0.f, 0.f);
+  float k = 0.0f;
+  if (j < n) {
+    const float d = D ? D[j] : 0.0f;
+    const float fl = d > eps ? d : eps;
+    const float id = fl > 0.0f ? 1.0f / fl : INFINITY;
+    k = A[j] * kInv4Pi;
+    if (d != d) k = NAN;
+    a = make_float4(P[j], P[n + j], P[2 * n + j], id);
+    b = make_float4(k * N[j], k * N[n + j], k * N[2 * n + j], 0.0f);
+  }
+  src[2 * j] = a;
+  src[2 * j + 1] = b;
+  kk[j] = k;
+}
+
+// Sum of `split` partials of accumulator `a` for query i, in split order.
+__device__ __forceinline__ float combine(const float* part, int split, int64_t mpad, int a, int64_t i,
+                                         bool kahan) {
+  float s = 0.0f, c = 0.0f;
+  for (int p = 0; p < split; ++p) {
+    const float x = part[((int64_t)p * kNAcc + a) * mpad + i];
+    if (kahan) {
+      const float y = x - c;
+      const float t = s + y;
+      c = (t - s) - y;
+      s = t;
+    } else {
+      s += x;
+    }
+  }
+  return kahan ? s - c : s;
+}
+
+// Block-wide FP64 sum (deterministic: fixed shuffle tree, then fixed LDS order).
+__device__ double block_sum(double v, double* lds) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[wv] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) r += lds[k];
+  return r;  // valid on thread 0
+}
+
+// Evaluation epilogue: combine splits; w, grad = (3 or 1) A - B; FP64 block partial of w.
+__global__ __launch_bounds__(kRedBlock) void k_combine(const float* __restrict__ part, int split,
+                                                       int64_t mpad, int64_t m, bool grad,
+                                                       float ascale, bool kahan,
+                                                       float* __restrict__ wout,
+                                                       float* __restrict__ gout,
+                                                       double* __restrict__ blk) {
+  __shared__ double lds[kRedBlock / 64];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double wv = 0.0;
+  if (i < m) {
+    const int na = grad ? kNAcc : 1;
+    float w;
+    if (na == 1) {
+      // eval-only partials are laid out [split][1][mpad]
+      float s = 0.0f, c = 0.0f;
+      for (int p = 0; p < split; ++p) {
+        const float x = part[(int64_t)p * mpad + i];
+        if (kahan) {
+          const float y = x - c;
+          const float t = s + y;
+          c = (t - s) - y;
+          s = t;
+        } else {
+          s += x;
+        }
+      }
+      w = kahan ? s - c : s;
+    } else {
+      w = combine(part, split, mpad, 0, i, kahan);
+      for (int d = 0; d < 3; ++d) {
+        const float A = combine(part, split, mpad, 1 + d, i, kahan);
+        const float B = combine(part, split, mpad, 4 + d, i, kahan);
+        gout[d * m + i] = fmaf(ascale, A, -B);
+      }
+    }
+    if (wout) wout[i] = w;
+    wv = (double)w;
+  }
+  const double bs = block_sum(wv, lds);
+  if (threadIdx.x == 0) blk[blockIdx.x] = bs;
+}
+
+// Iteration epilogue (Eq. 7): n_new = -grad/|grad| (kept when |grad| is 0 or not finite),
+// written in place; restage m for the next iteration; theta_i (degrees, FP64); FP64 block
+// partials of w and of the chord |n_new - n_old|.
+__global__ __launch_bounds__(kRedBlock) void k_update(const float* __restrict__ part, int split,
+                                                      int64_t mpad, int64_t n, float ascale,
+                                                      bool kahan, const float* __restrict__ kk,
+                                                      float* __restrict__ N,
+                                                      float4* __restrict__ src,
+                                                      double* __restrict__ theta,
+                                                      double* __restrict__ blk, int nblk) {
+  __shared__ double lds[kRedBlock / 64];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double wv = 0.0, cv = 0.0;
+  if (i < n) {
+    const float w = combine(part, split, mpad, 0, i, kahan);
+    float g[3];
+    for (int d = 0; d < 3; ++d) {
+      const float A = combine(part, split, mpad, 1 + d, i, kahan);
+      const float B = combine(part, split, mpad, 4 + d, i, kahan);
+      g[d] = fmaf(ascale, A, -B);
+    }
+    const float o0 = N[i], o1 = N[n + i], o2 = N[2 * n + i];
+    const double gl = sqrt((double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2]);
+    float n0 = o0, n1 = o1, n2 = o2;
+    if (gl > 0.0 && gl <= 1.7976931348623157e308) {
+      n0 = (float)(-(double)g[0] / gl);
+      n1 = (float)(-(double)g[1] / gl);
+      n2 = (float)(-(double)g[2] / gl);
+    }
+    const double e0 = (double)n0 - o0, e1 = (double)n1 - o1, e2 = (double)n2 - o2;
+    const double ch = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+    const double h = 0.5 * ch;
+    theta[i] = 2.0 * asin(h < 1.0 ? h : 1.0) * kRadToDeg;
+    N[i] = n0;
+    N[n + i] = n1;
+    N[2 * n + i] = n2;
+    const float k = kk[i];
+    src[2 * i + 1] = make_float4(k * n0, k * n1, k * n2, 0.0f);
+    wv = (double)w;
+    cv = ch;
+  }
+  const double bw = block_sum(wv, lds);
+  const double bc = block_sum(cv, lds);
+  if (threadIdx.x == 0) {
+    blk[blockIdx.x] = bw;
+    blk[nblk + blockIdx.x] = bc;
+  }
+}
+
+// Fixed-order sum of the block partials: stats[0] = sum w / n, stats[2] = sum chord / n;
+// also resets the radix-select state for k largest values.
+__global__ __launch_bounds__(kRedBlock) void k_sums(const double* __restrict__ blk, int nblk,
+                                                    int64_t n, int64_t k, int with_chord,
+                                                    double* __restrict__ stats,
+                                                    uint32_t* __restrict__ hist,
+                                                    uint64_t* __restrict__ sel) {
+  __shared__ double lds[kRedBlock / 64];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+    a += blk[i];
+    if (with_chord) b += blk[nblk + i];
+  }
+  const double sa = block_sum(a, lds);
+  const double sb = block_sum(b, lds);
+  if (threadIdx.x == 0) {
+    stats[0] = sa / (double)n;
+    stats[2] = sb / (double)n;
+    sel[0] = 0;
+    sel[1] = (uint64_t)k;
+  }
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+}
+
+// One radix-select pass over the FP64 bit patterns (non-negative doubles order like
+// unsigned integers): histogram of digit (bits >> shift) & 255 among values whose higher
+// bits equal the prefix selected so far.
+__global__ __launch_bounds__(kRedBlock) void k_radix_hist(const double* __restrict__ theta,
+                                                          int64_t n, int shift,
+                                                          const uint64_t* __restrict__ sel,
+                                                          uint32_t* __restrict__ hist) {
+  __shared__ uint32_t lh[256];
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) lh[i] = 0;
+  __syncthreads();
+  const uint64_t prefix = sel[0];
+  const uint64_t hmask = shift >= 56 ? 0ull : (~0ull << (shift + 8));
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t bits = (uint64_t)__double_as_longlong(theta[i]);
+    if ((bits & hmask) == (prefix & hmask)) atomicAdd(&lh[(bits >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 256; i += blockDim.x)
+    if (lh[i]) atomicAdd(&hist[i], lh[i]);
+}
+
+// Picks the digit holding the k-th largest value, extends the prefix, clears the histogram.
+__global__ void k_radix_select(int shift, uint64_t* __restrict__ sel, uint32_t* __restrict__ hist) {
+  if (threadIdx.x == 0) {
+    uint64_t krem = sel[1];
+    uint64_t prefix = sel[0];
+    for (int d = 255; d >= 0; --d) {
+      const uint64_t c = hist[d];
+      if (krem <= c) {
+        prefix |= (uint64_t)d << shift;
+        break;
+      }
+      krem -= c;
+    }
+    sel[0] = prefix;
+    sel[1] = krem;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+}
+
+// FP64 block partials of the sum of theta_i strictly above the selected k-th largest value.
+__global__ __launch_bounds__(kRedBlock) void k_top_partial(const double* __restrict__ theta, int64_t n,
+                                                           const uint64_t* __restrict__ sel,
+                                                           double* __restrict__ blk) {
+  __shared__ double lds[kRedBlock / 64];
+  const uint64_t thr = sel[0];
+  double v = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double x = theta[i];
+    if ((uint64_t)__double_as_longlong(x) > thr) v += x;
+  }
+  const double b = block_sum(v, lds);
+  if (threadIdx.x == 0) blk[blockIdx.x] = b;
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_top_final(const double* __restrict__ blk, int nblk,
+                                                         int64_t k, const uint64_t* __restrict__ sel,
+                                                         double* __restrict__ stats) {
+  __shared__ double lds[kRedBlock / 64];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) a += blk[i];
+  const double s = block_sum(a, lds);
+  if (threadIdx.x == 0) {
+    const double t = __longlong_as_double((long long)sel[0]);
+    stats[1] = (s + (double)sel[1] * t) / (double)k;
+  }
+}
+
+// SplitMix64 output number t of the stream started at `seed` (Steele, Lea, Flood 2014).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t t) {
+  uint64_t z = seed + (t + 1ull) * 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_random_normals(uint64_t seed, int64_t n, float* __restrict__ N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float u0 = (float)(splitmix64(seed, 2ull * i) >> 40) * 0x1p-24f;
+  const float u1 = (float)(splitmix64(seed, 2ull * i + 1ull) >> 40) * 0x1p-24f;
+  const float z = 1.0f - 2.0f * u0;                 // exact
+  const float rr = sqrtf((1.0f - z) * (1.0f + z));  // one rounding before the sqrt
+  float sn, cs;
+  sincosf(6.28318530717958647692f * u1, &sn, &cs);
+  N[i] = rr * cs;
+  N[n + i] = rr * sn;
+  N[2 * n + i] = z;
+}
+
+template <int QPT, bool GRAD, bool SCREENED, bool KAHAN>
+void launch_gwn_t(dim3 grid, hipStream_t st, const float* Q, int64_t m, const GwnWork& w,
+                  int64_t tps, float s) {
+  const float neg_s_log2e = -s * 1.4426950408889634f;
+  hipLaunchKernelGGL((k_gwn<QPT, GRAD, SCREENED, KAHAN>), grid, dim3(kBlock), 0, st, Q, m, w.src,
+                     w.ntiles, tps, s, neg_s_log2e, s * s, w.part, w.mpad);
+}
+
+}  // namespace
+
+int choose_split(int64_t n_src, int64_t n_qry, int requested) {
+  const int64_t ntiles = cdiv(n_src, kTile);
+  if (requested > 0) return (int)std::min<int64_t>(std::min<int64_t>(requested, kMaxSplit), ntiles);
+  const int64_t qblocks = cdiv(n_qry, kQBlock);
+  // aim for >= 2048 blocks (8 per CU) while every split keeps >= 8 tiles
+  int64_t s = cdiv(2048, qblocks);
+  s = std::min<int64_t>(s, std::max<int64_t>(1, ntiles / 8));
+  s = std::max<int64_t>(1, std::min<int64_t>(s, kMaxSplit));
+  return (int)s;
+}
+
+size_t carve_gwn(Carver& c, int64_t n_src, int64_t n_qry, int split, GwnWork* out) {
+  GwnWork w{};
+  w.ntiles = cdiv(n_src, kTile);
+  w.npad = w.ntiles * kTile;
+  w.mpad = cdiv(n_qry, kQBlock) * kQBlock;
+  w.split = split;
+  w.nblk = (int)cdiv(std::max(n_src, n_qry), kRedBlock);
+  const size_t start = c.used;
+  w.src = c.take<float4>(2 * (size_t)w.npad);
+  w.part = c.take<float>((size_t)split * kNAcc * (size_t)w.mpad);
+  w.kk = c.take<float>((size_t)w.npad);
+  w.theta = c.take<double>((size_t)std::max(n_src, n_qry));
+  w.blk = c.take<double>(2 * (size_t)w.nblk);
+  w.stats = c.take<double>(4);
+  w.hist = c.take<uint32_t>(256);
+  w.sel = c.take<uint64_t>(2);
+  if (out) *out = w;
+  return c.used - start;
+}
+
+dwg_status launch_stage(const float* P, const float* N, const float* area, const float* delta,
+                        int64_t n, float eps, const GwnWork& w, hipStream_t stream) {
+  hipLaunchKernelGGL(k_stage, dim3((unsigned)cdiv(w.npad, 256)), dim3(256), 0, stream, P, N, area,
+                     delta, n, w.npad, eps, w.src, w.kk);
+  DWG_TRY_LAUNCH();
+  return DWG_OK;
+}
+
+dwg_status launch_gwn(const float* Q, int64_t m, const dwg_kernel_params& kp, bool grad,
+                      const GwnWork& w, hipStream_t stream) {
+  const int64_t qblocks = cdiv(m, kQBlock);
+  const int64_t tps = cdiv(w.ntiles, w.split);
+  dim3 grid((unsigned)qblocks, (unsigned)w.split);
+  const bool scr = kp.lambda > 0.0f;
+  const bool kah = kp.compensated != 0;
+  const float s = sqrtf(kp.lambda);
+#define DWG_GWN_CASE(G, S, K) \
+  if (grad == G && scr == S && kah == K) launch_gwn_t<kQpt, G, S, K>(grid, stream, Q, m, w, tps, s);
+  DWG_GWN_CASE(true, false, true)
+  DWG_GWN_CASE(true, false, false)
+  DWG_GWN_CASE(true, true, true)
+  DWG_GWN_CASE(true, true, false)
+  DWG_GWN_CASE(false, false, true)
+  DWG_GWN_CASE(false, false, false)
+  DWG_GWN_CASE(false, true, true)
+  DWG_GWN_CASE(false, true, false)
+#undef DWG_GWN_CASE
+  DWG_TRY_LAUNCH();
+  return DWG_OK;
+}
+
+dwg_status launch_combine(int64_t m, const dwg_kernel_params& kp, bool grad, float* wout,
+                          float* gout, double* wmean, const GwnWork& w, hipStream_t stream) {
+  const int nb = (int)cdiv(m, kRedBlock);
+  const float ascale = kp.lambda > 0.0f ? 1.0f : 3.0f;
+  hipLaunchKernelGGL(k_combine, dim3(nb), dim3(kRedBlock), 0, stream, w.part, w.split, w.mpad, m, grad,
+                     ascale, kp.compensated != 0, wout, gout, w.blk);
+  DWG_TRY_LAUNCH();
+  if (wmean) {
+    hipLaunchKernelGGL(k_sums, dim3(1), dim3(kRedBlock), 0, stream, w.blk, nb, m, (int64_t)1, 0,
+                       w.stats, w.hist, w.sel);
+    DWG_TRY_LAUNCH();
+    DWG_TRY_HIP(hipMemcpyAsync(wmean, w.stats, sizeof(double), hipMemcpyDeviceToDevice, stream));
+  }
+  return DWG_OK;
+}
+
+dwg_status launch_update(int64_t n, const float* area, const dwg_kernel_params& kp, float* N,
+                         const GwnWork& w, hipStream_t stream) {
+  (void)area;
+  const int nb = (int)cdiv(n, kRedBlock);
+  const float ascale = kp.lambda > 0.0f ? 1.0f : 3.0f;
+  hipLaunchKernelGGL(k_update, dim3(nb), dim3(kRedBlock), 0, stream, w.part, w.split, w.mpad, n, ascale,
+                     kp.compensated != 0, w.kk, N, w.src, w.theta, w.blk, nb);
+  DWG_TRY_LAUNCH();
+  return DWG_OK;
+}
+
+static int64_t top_count(int64_t n, double top_frac) {
+  int64_t k = (int64_t)std::ceil(top_frac * (double)n);
+  if (k < 1) k = 1;
+  if (k > n) k = n;
+  return k;
+}
+
+dwg_status launch_stats(int64_t n, double top_frac, const GwnWork& w, hipStream_t stream) {
+  const int nb = (int)cdiv(n, kRedBlock);
+  const int64_t k = top_count(n, top_frac);
+  hipLaunchKernelGGL(k_sums, dim3(1), dim3(kRedBlock), 0, stream, w.blk, nb, n, k, 1, w.stats, w.hist,
+                     w.sel);
+  DWG_TRY_LAUNCH();
+  const int hb = (int)std::min<int64_t>(cdiv(n, kRedBlock), 1024);
+  for (int shift = 56; shift >= 0; shift -= 8) {
+    hipLaunchKernelGGL(k_radix_hist, dim3(hb), dim3(kRedBlock), 0, stream, w.theta, n, shift, w.sel,
+                       w.hist);
+    DWG_TRY_LAUNCH();
+    hipLaunchKernelGGL(k_radix_select, dim3(1), dim3(256), 0, stream, shift, w.sel, w.hist);
+    DWG_TRY_LAUNCH();
+  }
+  hipLaunchKernelGGL(k_top_partial, dim3(hb), dim3(kRedBlock), 0, stream, w.theta, n, w.sel, w.blk);
+  DWG_TRY_LAUNCH();
+  hipLaunchKernelGGL(k_top_final, dim3(1), dim3(kRedBlock), 0, stream, w.blk, hb, k, w.sel, w.stats);
+  DWG_TRY_LAUNCH();
+  return DWG_OK;
+}
+
+dwg_status launch_random_normals(uint64_t seed, int64_t n, float* N, hipStream_t stream) {
+  hipLaunchKernelGGL(k_random_normals, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, stream, seed, n, N);
+  DWG_TRY_LAUNCH();
+  return DWG_OK;
+}
+
+}  // namespace dwg

@@ -1,0 +1,453 @@
+// Exact k-nearest-neighbour search on a uniform grid, the kernel radius delta (Sec. 5.2
+// "Poisson Kernels": mean distance to the k nearest neighbours) and the k = 16 anchor
+// features of the learned initial normals.
+//
+// Grid build: bounding box (deterministic two-stage min/max), cell size from the box
+// volume with at most ~8 cells per reference point, counting sort of the reference points
+// by cell (atomic cursors; the order inside a cell is arbitrary, which is harmless because
+// candidates are ranked by the pair (squared distance, index)). Query: one thread per query
+// walks Chebyshev rings of cells around its own cell and keeps the k best candidates in
+// registers; it stops once the k-th best distance is below the distance to the next ring.
+#include <cfloat>
+#include <cmath>
+
+#include "dwg_internal.h"
+
+namespace dwg {
+namespace {
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 4;  // elements per thread in the block scan
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+struct GridParams {
+  float ox, oy, oz;  // origin (bbox min)
+  float h, ih;       // cell size and its inverse
+  int nx, ny, nz;
+  int64_t ncells;
+};
+
+__global__ __launch_bounds__(256) void k_bbox_partial(const float* __restrict__ R, int64_t n,
+                                                      float* __restrict__ part) {
+  __shared__ float lds[6][256];
+  float mn[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, mx[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    for (int d = 0; d < 3; ++d) {
+      const float v = R[d * n + i];
+      mn[d] = fminf(mn[d], v);
+      mx[d] = fmaxf(mx[d], v);
+    }
+  }
+  for (int d = 0; d < 3; ++d) {
+    lds[d][threadIdx.x] = mn[d];
+    lds[3 + d][threadIdx.x] = mx[d];
+  }
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int d = 0; d < 3; ++d) {
+        lds[d][threadIdx.x] = fminf(lds[d][threadIdx.x], lds[d][threadIdx.x + s]);
+        lds[3 + d][threadIdx.x] = fmaxf(lds[3 + d][threadIdx.x], lds[3 + d][threadIdx.x + s]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = lds[threadIdx.x][0];
+}
+
+// Final bbox and grid parameters (single thread; nblocks is small).
+__global__ void k_grid_params(const float* __restrict__ part, int nblocks, int64_t n,
+                              int64_t max_cells, GridParams* __restrict__ gp) {
+  if (threadIdx.x != 0) return;
+  float mn[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, mx[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
+  for (int b = 0; b < nblocks; ++b)
+    for (int d = 0; d < 3; ++d) {
+      mn[d] = fminf(mn[d], part[b * 6 + d]);
+      mx[d] = fmaxf(mx[d], part[b * 6 + 3 + d]);
+    }
+  double ext[3];
+  double emax = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    ext[d] = (double)mx[d] - (double)mn[d];
+    emax = fmax(emax, ext[d]);
+  }
+  if (!(emax > 0.0)) emax = 1.0;
+  // slabs thinner than 1e-3 of the largest extent count as that thickness for the volume
+  double vol = 1.0;
+  for (int d = 0; d < 3; ++d) vol *= fmax(ext[d], 1e-3 * emax);
+  double h = cbrt(vol / (double)max_cells);
+  // every point must fall inside the grid (no clamping of interior points): grow h until
+  // the uncapped cell counts multiply to at most max_cells
+  double dd[3];
+  for (;;) {
+    double cells = 1.0;
+    for (int d = 0; d < 3; ++d) {
+      dd[d] = floor(ext[d] / h) + 1.0;
+      cells *= dd[d];
+    }
+    if (cells <= (double)max_cells) break;
+    h *= 1.05;
+  }
+  int dims[3] = {(int)dd[0], (int)dd[1], (int)dd[2]};
+  GridParams g;
+  g.ox = mn[0];
+  g.oy = mn[1];
+  g.oz = mn[2];
+  g.h = (float)h;
+  g.ih = (float)(1.0 / h);
+  g.nx = dims[0];
+  g.ny = dims[1];
+  g.nz = dims[2];
+  g.ncells = (int64_t)dims[0] * dims[1] * dims[2];
+  *gp = g;
+}
+
+__device__ __forceinline__ void cell_of(const GridParams& g, float x, float y, float z, int& cx,
+                                        int& cy, int& cz) {
+  cx = min(max((int)floorf((x - g.ox) * g.ih), 0), g.nx - 1);
+  cy = min(max((int)floorf((y - g.oy) * g.ih), 0), g.ny - 1);
+  cz = min(max((int)floorf((z - g.oz) * g.ih), 0), g.nz - 1);
+}
+
+__global__ void k_zero_i32(int32_t* __restrict__ a, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = 0;
+}
+
+__global__ void k_cell_count(const float* __restrict__ R, int64_t n, const GridParams* __restrict__ gp,
+                             int32_t* __restrict__ key, int32_t* __restrict__ count) {
+  const GridParams g = *gp;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int cx, cy, cz;
+    cell_of(g, R[i], R[n + i], R[2 * n + i], cx, cy, cz);
+    const int32_t c = (int32_t)(((int64_t)cz * g.ny + cy) * g.nx + cx);
+    key[i] = c;
+    atomicAdd(&count[c], 1);
+  }
+}
+
+// Exclusive scan, stage 1: each block scans kScanTile elements of `a` in place and writes
+// its total to `sums[block]`. Elements past `n` read as 0.
+__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(int32_t* __restrict__ a, int64_t n,
+                                                           int32_t* __restrict__ sums) {
+  __shared__ int32_t lds[kScanBlock];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int32_t v[kScanItems];
+  int32_t tot = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < n) ? a[base + k] : 0;
+    tot += v[k];
+  }
+  lds[threadIdx.x] = tot;
+  __syncthreads();
+  for (int off = 1; off < kScanBlock; off <<= 1) {
+    const int32_t x = ((int)threadIdx.x >= off) ? lds[threadIdx.x - off] : 0;
+    __syncthreads();
+    lds[threadIdx.x] += x;
+    __syncthreads();
+  }
+  int32_t run = lds[threadIdx.x] - tot;  // exclusive prefix of this thread
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) a[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == kScanBlock - 1) sums[blockIdx.x] = lds[kScanBlock - 1];
+}
+
+// Stage 2: one block scans the tile totals serially in chunks (exclusive) and writes the
+// grand total to a[n] (the end marker of the last cell).
+__global__ __launch_bounds__(kScanBlock) void k_scan_sums(int32_t* __restrict__ sums, int64_t nt,
+                                                          int32_t* __restrict__ a, int64_t n) {
+  __shared__ int32_t lds[kScanBlock];
+  const int64_t per = (nt + kScanBlock - 1) / kScanBlock;
+  const int64_t b0 = (int64_t)threadIdx.x * per, b1 = min(b0 + per, nt);
+  int32_t tot = 0;
+  for (int64_t i = b0; i < b1; ++i) tot += sums[i];
+  lds[threadIdx.x] = tot;
+  __syncthreads();
+  for (int off = 1; off < kScanBlock; off <<= 1) {
+    const int32_t x = ((int)threadIdx.x >= off) ? lds[threadIdx.x - off] : 0;
+    __syncthreads();
+    lds[threadIdx.x] += x;
+    __syncthreads();
+  }
+  int32_t run = lds[threadIdx.x] - tot;
+  for (int64_t i = b0; i < b1; ++i) {
+    const int32_t x = sums[i];
+    sums[i] = run;
+    run += x;
+  }
+  if (threadIdx.x == kScanBlock - 1) a[n] = lds[kScanBlock - 1];
+}
+
+__global__ void k_scan_add(int32_t* __restrict__ a, int64_t n, const int32_t* __restrict__ sums) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] += sums[i / kScanTile];
+}
+
+// Scatter reference points into cell order: sorted[pos] = (x, y, z, index bits).
+__global__ void k_scatter(const float* __restrict__ R, int64_t n, const int32_t* __restrict__ key,
+                          const int32_t* __restrict__ start, int32_t* __restrict__ cursor,
+                          float4* __restrict__ sorted) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t c = key[i];
+    const int32_t pos = start[c] + atomicAdd(&cursor[c], 1);
+    sorted[pos] = make_float4(R[i], R[n + i], R[2 * n + i], __int_as_float((int)i));
+  }
+}
+
+// (d2, idx) < (e2, jdx) lexicographically
+__device__ __forceinline__ bool less_pair(float d2, int i, float e2, int j) {
+  return d2 < e2 || (d2 == e2 && i < j);
+}
+
+// skip_mode: 0 none; 1 reference i == query i; 2 reference i / stride when i % stride == 0.
+template <int K>
+__global__ __launch_bounds__(256) void k_knn(const float* __restrict__ Q, int64_t m,
+                                             const GridParams* __restrict__ gp,
+                                             const int32_t* __restrict__ start,
+                                             const float4* __restrict__ sorted, int skip_mode,
+                                             int64_t stride, int32_t* __restrict__ idx,
+                                             float* __restrict__ dist) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  const GridParams g = *gp;
+  const float qx = Q[q], qy = Q[m + q], qz = Q[2 * m + q];
+  int skip = -1;
+  if (skip_mode == 1) skip = (int)q;
+  if (skip_mode == 2 && (q % stride) == 0) skip = (int)(q / stride);
+  float bd[K];
+  int bi[K];
+#pragma unroll
+  for (int s = 0; s < K; ++s) {
+    bd[s] = INFINITY;
+    bi[s] = 0x7fffffff;
+  }
+  int cx, cy, cz;
+  cell_of(g, qx, qy, qz, cx, cy, cz);
+  const int rmax = max(g.nx, max(g.ny, g.nz));
+  for (int r = 0; r <= rmax; ++r) {
+    for (int dz = -r; dz <= r; ++dz) {
+      const int z = cz + dz;
+      if (z < 0 || z >= g.nz) continue;
+      for (int dy = -r; dy <= r; ++dy) {
+        const int y = cy + dy;
+        if (y < 0 || y >= g.ny) continue;
+        const bool shell = (dz == -r || dz == r || dy == -r || dy == r);
+        const int xstep = shell ? 1 : max(2 * r, 1);
+        for (int dx = -r; dx <= r; dx += xstep) {
+          const int x = cx + dx;
+          if (x < 0 || x >= g.nx) continue;
+          const int64_t c = ((int64_t)z * g.ny + y) * g.nx + x;
+          const int32_t e = start[c + 1];
+          for (int32_t p = start[c]; p < e; ++p) {
+            const float4 s = sorted[p];
+            const int j = __float_as_int(s.w);
+            if (j == skip) continue;
+            const float ex = s.x - qx, ey = s.y - qy, ez = s.z - qz;
+            const float d2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+            if (!less_pair(d2, j, bd[K - 1], bi[K - 1])) continue;
+            // insertion into the sorted list (fully unrolled, register resident)
+#pragma unroll
+            for (int t = K - 1; t >= 1; --t) {
+              const bool up = less_pair(d2, j, bd[t - 1], bi[t - 1]);
+              const bool here = !up && less_pair(d2, j, bd[t], bi[t]);
+              const float nd = up ? bd[t - 1] : (here ? d2 : bd[t]);
+              const int ni = up ? bi[t - 1] : (here ? j : bi[t]);
+              bd[t] = nd;
+              bi[t] = ni;
+            }
+            if (less_pair(d2, j, bd[0], bi[0])) {
+              bd[0] = d2;
+              bi[0] = j;
+            }
+          }
+        }
+      }
+    }
+    // every cell of ring r + 1 or beyond lies at least r * h away from the query
+    const float lb = (float)r * g.h;
+    if (bd[K - 1] < INFINITY && bd[K - 1] <= lb * lb) break;
+  }
+#pragma unroll
+  for (int s = 0; s < K; ++s) {
+    idx[q * K + s] = bi[s];
+    if (dist) dist[q * K + s] = sqrtf(bd[s]);
+  }
+}
+
+__global__ void k_delta(const float* __restrict__ dist, int64_t n, int k, float scale,
+                        float* __restrict__ delta) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.0f;
+  for (int t = 0; t < k; ++t) s += dist[i * k + t];
+  delta[i] = scale * (s / (float)k);
+}
+
+__global__ void k_gather_anchors(const float* __restrict__ P, int64_t n, int64_t stride, int64_t na,
+                                 float* __restrict__ A) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= na) return;
+  const int64_t i = a * stride;
+  A[a] = P[i];
+  A[na + a] = P[n + i];
+  A[2 * na + a] = P[2 * n + i];
+}
+
+// feat[i][3k + d] = (anchor_k - p_i)_d / s_i, s_i = mean of the 16 anchor distances.
+__global__ void k_features(const float* __restrict__ P, int64_t n, const float* __restrict__ A,
+                           int64_t na, const int32_t* __restrict__ idx,
+                           const float* __restrict__ dist, float* __restrict__ feat) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.0f;
+  for (int t = 0; t < DWG_FEAT_K; ++t) s += dist[i * DWG_FEAT_K + t];
+  s *= (1.0f / DWG_FEAT_K);
+  const float is = s > 0.0f ? 1.0f / s : 0.0f;
+  const float px = P[i], py = P[n + i], pz = P[2 * n + i];
+  for (int t = 0; t < DWG_FEAT_K; ++t) {
+    const int64_t a = idx[i * DWG_FEAT_K + t];
+    feat[i * DWG_MLP_IN + 3 * t + 0] = (A[a] - px) * is;
+    feat[i * DWG_MLP_IN + 3 * t + 1] = (A[na + a] - py) * is;
+    feat[i * DWG_MLP_IN + 3 * t + 2] = (A[2 * na + a] - pz) * is;
+  }
+}
+
+struct KnnWork {
+  float* bbox_part;  // [kBboxBlocks * 6]
+  GridParams* gp;
+  int32_t* key;      // [nr]
+  int32_t* start;    // [max_cells + 1]
+  int32_t* cursor;   // [max_cells]
+  int32_t* sums;     // [tiles]
+  float4* sorted;    // [nr]
+};
+
+constexpr int kBboxBlocks = 256;
+
+int64_t max_cells_for(int64_t nr) { return std::max<int64_t>(8 * nr, 64); }
+
+size_t carve_knn(Carver& c, int64_t nr, KnnWork* out) {
+  const int64_t mc = max_cells_for(nr);
+  const size_t s0 = c.used;
+  KnnWork w;
+  w.bbox_part = c.take<float>(kBboxBlocks * 6);
+  w.gp = c.take<GridParams>(1);
+  w.key = c.take<int32_t>((size_t)nr);
+  w.start = c.take<int32_t>((size_t)mc + 1);
+  w.cursor = c.take<int32_t>((size_t)mc);
+  w.sums = c.take<int32_t>((size_t)cdiv(mc, kScanTile) + 1);
+  w.sorted = c.take<float4>((size_t)nr);
+  if (out) *out = w;
+  return c.used - s0;
+}
+
+unsigned grid_for(int64_t n, int block = 256, int64_t cap = 65535) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, block), cap));
+}
+
+template <int K>
+void launch_knn_k(int64_t m, hipStream_t st, const float* Q, const KnnWork& w, int skip_mode,
+                  int64_t stride, int32_t* idx, float* dist) {
+  hipLaunchKernelGGL(k_knn<K>, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, st, Q, m, w.gp, w.start,
+                     w.sorted, skip_mode, stride, idx, dist);
+}
+
+dwg_status build_grid(const float* R, int64_t nr, const KnnWork& w, hipStream_t st) {
+  const int64_t mc = max_cells_for(nr);
+  hipLaunchKernelGGL(k_bbox_partial, dim3(kBboxBlocks), dim3(256), 0, st, R, nr, w.bbox_part);
+  DWG_TRY_LAUNCH();
+  hipLaunchKernelGGL(k_grid_params, dim3(1), dim3(64), 0, st, w.bbox_part, kBboxBlocks, nr, mc, w.gp);
+  DWG_TRY_LAUNCH();
+  // counts and cursors over the largest possible grid (the actual grid has <= mc cells)
+  hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(mc + 1)), dim3(256), 0, st, w.start, mc + 1);
+  hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(mc)), dim3(256), 0, st, w.cursor, mc);
+  DWG_TRY_LAUNCH();
+  hipLaunchKernelGGL(k_cell_count, dim3(grid_for(nr)), dim3(256), 0, st, R, nr, w.gp, w.key, w.start);
+  DWG_TRY_LAUNCH();
+  const int64_t nt = cdiv(mc, kScanTile);
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(kScanBlock), 0, st, w.start, mc, w.sums);
+  DWG_TRY_LAUNCH();
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, w.sums, nt, w.start, mc);
+  DWG_TRY_LAUNCH();
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)cdiv(mc, 256)), dim3(256), 0, st, w.start, mc, w.sums);
+  DWG_TRY_LAUNCH();
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for(nr)), dim3(256), 0, st, R, nr, w.key, w.start, w.cursor,
+                     w.sorted);
+  DWG_TRY_LAUNCH();
+  return DWG_OK;
+}
+
+dwg_status knn_query(const float* Q, int64_t m, const KnnWork& w, int skip_mode, int64_t stride, int k,
+                     int32_t* idx, float* dist, hipStream_t st) {
+  switch (k) {
+#define DWG_K(KK) \
+  case KK: launch_knn_k<KK>(m, st, Q, w, skip_mode, stride, idx, dist); break;
+    DWG_K(1) DWG_K(2) DWG_K(3) DWG_K(4) DWG_K(5) DWG_K(6) DWG_K(7) DWG_K(8)
+    DWG_K(9) DWG_K(10) DWG_K(11) DWG_K(12) DWG_K(13) DWG_K(14) DWG_K(15) DWG_K(16)
+#undef DWG_K
+    default: set_error("k out of range"); return DWG_E_INVALID;
+  }
+  DWG_TRY_LAUNCH();
+  return DWG_OK;
+}
+
+}  // namespace
+
+size_t knn_ws_bytes(int64_t n_ref, int64_t n_qry) {
+  (void)n_qry;
+  Carver c(nullptr);
+  carve_knn(c, n_ref, nullptr);
+  return c.used;
+}
+
+dwg_status knn_run(const float* R, int64_t nr, const float* Q, int64_t m, int self_skip,
+                   const int64_t* skip_stride, int k, int32_t* idx, float* dist, void* ws,
+                   size_t ws_bytes, hipStream_t stream) {
+  (void)ws_bytes;
+  (void)skip_stride;
+  Carver c(ws);
+  KnnWork w;
+  carve_knn(c, nr, &w);
+  dwg_status s = build_grid(R, nr, w, stream);
+  if (s != DWG_OK) return s;
+  return knn_query(Q, m, w, self_skip ? 1 : 0, 1, k, idx, dist, stream);
+}
+
+dwg_status delta_from_knn(const float* dist, int64_t n, int k, float scale, float* delta,
+                          hipStream_t stream) {
+  hipLaunchKernelGGL(k_delta, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, stream, dist, n, k, scale, delta);
+  DWG_TRY_LAUNCH();
+  return DWG_OK;
+}
+
+// Anchors: every stride-th point, stride = max(1, n / n_anchor).
+dwg_status features_run(const float* P, int64_t n, int64_t n_anchor, float* feat, void* ws,
+                        size_t ws_bytes, hipStream_t stream) {
+  (void)ws_bytes;
+  const int64_t stride = std::max<int64_t>(1, n / n_anchor);
+  const int64_t na = cdiv(n, stride);
+  Carver c(ws);
+  float* A = c.take<float>(3 * (size_t)na);
+  int32_t* idx = c.take<int32_t>((size_t)n * DWG_FEAT_K);
+  float* dist = c.take<float>((size_t)n * DWG_FEAT_K);
+  KnnWork w;
+  carve_knn(c, na, &w);
+  hipLaunchKernelGGL(k_gather_anchors, dim3((unsigned)cdiv(na, 256)), dim3(256), 0, stream, P, n, stride,
+                     na, A);
+  DWG_TRY_LAUNCH();
+  dwg_status s = build_grid(A, na, w, stream);
+  if (s != DWG_OK) return s;
+  s = knn_query(P, n, w, 2, stride, DWG_FEAT_K, idx, dist, stream);
+  if (s != DWG_OK) return s;
+  hipLaunchKernelGGL(k_features, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, stream, P, n, A, na, idx,
+                     dist, feat);
+  DWG_TRY_LAUNCH();
+  return DWG_OK;
+}
+
+}  // namespace dwg

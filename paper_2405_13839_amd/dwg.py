@@ -1,0 +1,292 @@
+"""Python binding of libdwg (include/dwg.h): argument marshalling only.
+
+Every function takes and returns torch tensors on a ROCm device; the arithmetic runs in
+the library's HIP kernels on the tensor's device and on torch's current stream. The library
+must have been built (python -m paper_2405_13839_amd.build); importing this module on a
+machine without it raises ImportError -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdwg.so")
+
+DWG_OK, DWG_NOT_CONVERGED = 0, 1
+DWG_E_INVALID, DWG_E_WORKSPACE, DWG_E_DEVICE, DWG_E_NONFINITE, DWG_E_UNSUPPORTED = -1, -2, -3, -4, -5
+INIT_RANDOM, INIT_MLP = 0, 1
+MLP_IN, MLP_HID, MLP_OUT, FEAT_K = 48, 128, 3, 16
+
+
+class DwgError(RuntimeError):
+    def __init__(self, status: int, name: str, detail: str):
+        super().__init__(f"{name}: {detail}")
+        self.status = status
+
+
+class KernelParams(ctypes.Structure):
+    _fields_ = [("lam", ctypes.c_float), ("eps", ctypes.c_float), ("compensated", ctypes.c_int),
+                ("split", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
+
+
+class IterateParams(ctypes.Structure):
+    _fields_ = [("max_iters", ctypes.c_int), ("fixed_iters", ctypes.c_int), ("eps_deg", ctypes.c_double),
+                ("top_frac", ctypes.c_double)]
+
+
+class IterStat(ctypes.Structure):
+    _fields_ = [("wmean", ctypes.c_double), ("top_mean_deg", ctypes.c_double), ("mean_chord", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libdwg.so (after torch, so that both share torch's HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2405_13839_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, sz, f32, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t, ctypes.c_float, ctypes.c_int
+    kpp = ctypes.POINTER(KernelParams)
+    lib.dwg_version.restype = ctypes.c_char_p
+    lib.dwg_status_string.restype = ctypes.c_char_p
+    lib.dwg_status_string.argtypes = [i32]
+    lib.dwg_last_error.restype = ctypes.c_char_p
+    lib.dwg_workspace_bytes.restype = sz
+    lib.dwg_workspace_bytes.argtypes = [i64, i64, kpp]
+    lib.dwg_gwn_eval.argtypes = [vp, vp, vp, vp, i64, vp, i64, kpp, vp, vp, vp, sz, vp]
+    lib.dwg_gwn_grad.argtypes = [vp, vp, vp, vp, i64, vp, i64, kpp, vp, vp, vp, vp, sz, vp]
+    lib.dwg_iterate.argtypes = [vp, vp, vp, i64, vp, kpp, ctypes.POINTER(IterateParams),
+                                ctypes.POINTER(IterStat), ctypes.POINTER(ctypes.c_int), vp, sz, vp]
+    lib.dwg_init_normals.argtypes = [i32, ctypes.c_uint64, vp, i64, vp, vp, vp, sz, vp]
+    lib.dwg_knn.argtypes = [vp, i64, vp, i64, i32, i32, vp, vp, vp, sz, vp]
+    lib.dwg_delta_knn_mean.argtypes = [vp, i64, i32, f32, vp, vp, sz, vp]
+    lib.dwg_mlp_param_count.restype = i64
+    lib.dwg_features.argtypes = [vp, i64, i64, vp, vp, sz, vp]
+    lib.dwg_mlp_infer.argtypes = [vp, vp, i64, vp, vp, sz, vp]
+    lib.dwg_mlp_train_step.argtypes = [vp, vp, vp, i64, f32, vp, vp, vp, i64, vp, vp, vp, sz, vp]
+    for name in ["dwg_gwn_eval", "dwg_gwn_grad", "dwg_iterate", "dwg_init_normals", "dwg_knn",
+                 "dwg_delta_knn_mean", "dwg_features", "dwg_mlp_infer", "dwg_mlp_train_step"]:
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+EXPORTED = ["dwg_version", "dwg_status_string", "dwg_last_error", "dwg_workspace_bytes", "dwg_gwn_eval",
+            "dwg_gwn_grad", "dwg_iterate", "dwg_init_normals", "dwg_knn", "dwg_delta_knn_mean",
+            "dwg_mlp_param_count", "dwg_features", "dwg_mlp_infer", "dwg_mlp_train_step"]
+
+
+def version() -> str:
+    return load().dwg_version().decode()
+
+
+def _check(status: int, ok=(DWG_OK,)):
+    if status not in ok:
+        lib = load()
+        raise DwgError(status, lib.dwg_status_string(status).decode(), lib.dwg_last_error().decode())
+    return status
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(t, name, dtype=torch.float32, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a ROCm device (got {t.device})")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)} (got {tuple(t.shape)})")
+    return t
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+@dataclass
+class Params:
+    lam: float = 0.0
+    eps: float = 0.0
+    compensated: bool = True
+    split: int = 0
+
+    def c(self):
+        return KernelParams(float(self.lam), float(self.eps), int(bool(self.compensated)), int(self.split),
+                            (ctypes.c_int * 4)(0, 0, 0, 0))
+
+
+def workspace_bytes(n_src: int, n_qry: int, params: Params | None = None) -> int:
+    kp = (params or Params()).c()
+    return int(load().dwg_workspace_bytes(int(n_src), int(n_qry), ctypes.byref(kp)))
+
+
+def workspace(n_src: int, n_qry: int, device, params: Params | None = None) -> torch.Tensor:
+    return torch.empty(max(1, workspace_bytes(n_src, n_qry, params)), dtype=torch.uint8, device=device)
+
+
+def gwn(P, N, area, delta, Q, params: Params | None = None, grad=True, ws=None, want_wmean=False):
+    """w [m] and (if grad) grad w [3, m] of the (screened) GWN of the oriented cloud at Q."""
+    lib = load()
+    params = params or Params()
+    P = _dev(P, "P")
+    n = P.shape[1]
+    _dev(N, "N", shape=(3, n))
+    _dev(area, "area", shape=(n,))
+    if delta is not None:
+        _dev(delta, "delta", shape=(n,))
+    Q = _dev(Q, "Q")
+    m = Q.shape[1]
+    dev = P.device
+    if ws is None:
+        ws = workspace(n, m, dev, params)
+    w = torch.empty(m, dtype=torch.float32, device=dev)
+    wm = torch.empty(1, dtype=torch.float64, device=dev) if want_wmean else None
+    kp = params.c()
+    if grad:
+        g = torch.empty((3, m), dtype=torch.float32, device=dev)
+        _check(lib.dwg_gwn_grad(_ptr(P), _ptr(N), _ptr(area), _ptr(delta), n, _ptr(Q), m, ctypes.byref(kp), _ptr(w),
+                                _ptr(g), _ptr(wm), _ptr(ws), ws.numel(), _stream(dev)))
+        return (w, g, wm) if want_wmean else (w, g)
+    _check(lib.dwg_gwn_eval(_ptr(P), _ptr(N), _ptr(area), _ptr(delta), n, _ptr(Q), m, ctypes.byref(kp), _ptr(w),
+                            _ptr(wm), _ptr(ws), ws.numel(), _stream(dev)))
+    return (w, wm) if want_wmean else w
+
+
+def iterate(P, area, delta, N, params: Params | None = None, max_iters=50, fixed_iters=False, eps_deg=0.1,
+            top_frac=0.01, ws=None):
+    """Run Algorithm 1 in place on N ([3, n] float32). Returns (status, stats float64 [T, 3])."""
+    lib = load()
+    params = params or Params()
+    P = _dev(P, "P")
+    n = P.shape[1]
+    _dev(area, "area", shape=(n,))
+    if delta is not None:
+        _dev(delta, "delta", shape=(n,))
+    _dev(N, "N", shape=(3, n))
+    dev = P.device
+    if ws is None:
+        ws = workspace(n, n, dev, params)
+    kp = params.c()
+    ip = IterateParams(int(max_iters), int(bool(fixed_iters)), float(eps_deg), float(top_frac))
+    stats = (IterStat * int(max_iters))()
+    done = ctypes.c_int(0)
+    st = lib.dwg_iterate(_ptr(P), _ptr(area), _ptr(delta), n, _ptr(N), ctypes.byref(kp), ctypes.byref(ip), stats,
+                         ctypes.byref(done), _ptr(ws), ws.numel(), _stream(dev))
+    _check(st, ok=(DWG_OK, DWG_NOT_CONVERGED))
+    out = torch.tensor([[s.wmean, s.top_mean_deg, s.mean_chord] for s in stats[: done.value]], dtype=torch.float64)
+    return st, out
+
+
+def random_normals(n: int, seed: int, device) -> torch.Tensor:
+    lib = load()
+    N = torch.empty((3, n), dtype=torch.float32, device=device)
+    _check(lib.dwg_init_normals(INIT_RANDOM, ctypes.c_uint64(seed), None, n, None, _ptr(N), None, 0,
+                                _stream(N.device)))
+    return N
+
+
+def mlp_normals(P, mlp_params, ws=None) -> torch.Tensor:
+    lib = load()
+    P = _dev(P, "P")
+    n = P.shape[1]
+    _dev(mlp_params, "mlp_params", shape=(mlp_param_count(),))
+    if ws is None:
+        ws = workspace(n, n, P.device)
+    N = torch.empty((3, n), dtype=torch.float32, device=P.device)
+    _check(lib.dwg_init_normals(INIT_MLP, ctypes.c_uint64(0), _ptr(P), n, _ptr(mlp_params), _ptr(N), _ptr(ws),
+                                ws.numel(), _stream(P.device)))
+    return N
+
+
+def knn(R, Q, k: int, self_skip: bool = False, ws=None, want_dist=True):
+    """(idx int32 [m, k], dist float32 [m, k]) of the k nearest points of R for each query."""
+    lib = load()
+    R = _dev(R, "R")
+    Q = _dev(Q, "Q")
+    nr, m = R.shape[1], Q.shape[1]
+    if ws is None:
+        ws = workspace(nr, m, R.device)
+    idx = torch.empty((m, k), dtype=torch.int32, device=R.device)
+    dist = torch.empty((m, k), dtype=torch.float32, device=R.device) if want_dist else None
+    _check(lib.dwg_knn(_ptr(R), nr, _ptr(Q), m, int(bool(self_skip)), int(k), _ptr(idx), _ptr(dist), _ptr(ws),
+                       ws.numel(), _stream(R.device)))
+    return idx, dist
+
+
+def delta_knn_mean(P, k: int = 10, scale: float = 1.0, ws=None) -> torch.Tensor:
+    lib = load()
+    P = _dev(P, "P")
+    n = P.shape[1]
+    if ws is None:
+        ws = workspace(n, n, P.device)
+    out = torch.empty(n, dtype=torch.float32, device=P.device)
+    _check(lib.dwg_delta_knn_mean(_ptr(P), n, int(k), float(scale), _ptr(out), _ptr(ws), ws.numel(),
+                                  _stream(P.device)))
+    return out
+
+
+def mlp_param_count() -> int:
+    return int(load().dwg_mlp_param_count())
+
+
+def features(P, n_anchor: int = 4096, ws=None) -> torch.Tensor:
+    lib = load()
+    P = _dev(P, "P")
+    n = P.shape[1]
+    if ws is None:
+        ws = workspace(n, n, P.device)
+    out = torch.empty((n, MLP_IN), dtype=torch.float32, device=P.device)
+    _check(lib.dwg_features(_ptr(P), n, int(n_anchor), _ptr(out), _ptr(ws), ws.numel(), _stream(P.device)))
+    return out
+
+
+def mlp_infer(params, X, ws=None) -> torch.Tensor:
+    lib = load()
+    X = _dev(X, "X")
+    B = X.shape[0]
+    _dev(params, "params", shape=(mlp_param_count(),))
+    if ws is None:
+        ws = workspace(B, B, X.device)
+    Y = torch.empty((B, MLP_OUT), dtype=torch.float32, device=X.device)
+    _check(lib.dwg_mlp_infer(_ptr(params), _ptr(X), B, _ptr(Y), _ptr(ws), ws.numel(), _stream(X.device)))
+    return Y
+
+
+def mlp_train_step(params, adam_m, adam_v, step: int, lr: float, X, T, mask=None, ws=None, want_grad=False):
+    """One Adam step in place on params / adam_m / adam_v. Returns (loss tensor [1], grad or None)."""
+    lib = load()
+    X = _dev(X, "X")
+    B = X.shape[0]
+    npar = mlp_param_count()
+    for t, nm in [(params, "params"), (adam_m, "adam_m"), (adam_v, "adam_v")]:
+        _dev(t, nm, shape=(npar,))
+    _dev(T, "T", shape=(B, 3))
+    if mask is not None:
+        _dev(mask, "mask", dtype=torch.uint8, shape=(B,))
+    if ws is None:
+        ws = workspace(B, B, X.device)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    grad = torch.empty(npar, dtype=torch.float32, device=X.device) if want_grad else None
+    _check(lib.dwg_mlp_train_step(_ptr(params), _ptr(adam_m), _ptr(adam_v), int(step), float(lr), _ptr(X), _ptr(T),
+                                  _ptr(mask), B, _ptr(grad), _ptr(loss), _ptr(ws), ws.numel(), _stream(X.device)))
+    return loss, grad
+
+
+def top_count(n: int, top_frac: float = 0.01) -> int:
+    """Number of largest normal changes the convergence statistic averages."""
+    return max(1, min(n, int(math.ceil(top_frac * n))))

@@ -1,0 +1,107 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared symbol, and
+rejects bad arguments before its first HIP call (so fake non-NULL pointers are safe)."""
+import ctypes
+import os
+import re
+
+import pytest
+import torch  # noqa: F401  (loads the HIP runtime libdwg links against)
+
+from paper_2405_13839_amd import dwg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dwg.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(dwg.LIB_PATH), reason="libdwg.so not built")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dwg_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    lib = dwg.load()
+    names = declared_functions()
+    assert len(names) >= 14
+    for nm in names:
+        assert hasattr(lib, nm), nm
+    assert set(dwg.EXPORTED) == set(names)
+
+
+def test_version_and_status_strings():
+    lib = dwg.load()
+    assert "gfx950" in dwg.version()
+    assert lib.dwg_status_string(-2) == b"DWG_E_WORKSPACE"
+    assert lib.dwg_status_string(1) == b"DWG_NOT_CONVERGED"
+
+
+def test_workspace_bytes():
+    assert dwg.workspace_bytes(0, 10) == 0
+    a = dwg.workspace_bytes(1000, 1000)
+    b = dwg.workspace_bytes(100_000, 100_000)
+    assert 0 < a < b
+    assert b < 200 * 100_000 * 8  # O(n) bytes
+    # invalid kernel parameters make it report 0
+    assert dwg.workspace_bytes(1000, 1000, dwg.Params(lam=-1.0)) == 0
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails before any device access
+
+
+def _call_grad(n=10, m=10, kp=None, ws=FAKE, ws_bytes=1 << 40, P=FAKE, g=FAKE):
+    lib = dwg.load()
+    kp = kp or dwg.Params().c()
+    return lib.dwg_gwn_grad(P, FAKE, FAKE, None, n, FAKE, m, ctypes.byref(kp), None, g, None, ws, ws_bytes, None)
+
+
+def test_invalid_arguments_rejected_before_device():
+    assert _call_grad(P=None) == dwg.DWG_E_INVALID
+    assert _call_grad(g=None) == dwg.DWG_E_INVALID
+    assert _call_grad(n=0) == dwg.DWG_E_INVALID
+    assert _call_grad(m=-3) == dwg.DWG_E_INVALID
+    for bad in [dwg.Params(lam=-1), dwg.Params(lam=float("nan")), dwg.Params(eps=-1e-3), dwg.Params(split=65)]:
+        assert _call_grad(kp=bad.c()) == dwg.DWG_E_INVALID
+    kp = dwg.Params().c()
+    kp.reserved[2] = 1
+    assert _call_grad(kp=kp) == dwg.DWG_E_INVALID
+    assert b"reserved" in dwg.load().dwg_last_error()
+
+
+def test_workspace_too_small():
+    need = dwg.workspace_bytes(10, 10)
+    assert _call_grad(ws_bytes=need - 1) == dwg.DWG_E_WORKSPACE
+    assert _call_grad(ws=None, ws_bytes=0) == dwg.DWG_E_WORKSPACE
+    assert b"workspace" in dwg.load().dwg_last_error()
+
+
+def test_iterate_parameter_validation():
+    lib = dwg.load()
+    kp = dwg.Params().c()
+    for ip in [dwg.IterateParams(0, 0, 0.1, 0.01), dwg.IterateParams(5, 0, -1.0, 0.01),
+               dwg.IterateParams(5, 0, 0.1, 0.0), dwg.IterateParams(5, 0, 0.1, 1.5), dwg.IterateParams(5, 2, 0.1, 0.01)]:
+        done = ctypes.c_int(7)
+        st = lib.dwg_iterate(FAKE, FAKE, None, 100, FAKE, ctypes.byref(kp), ctypes.byref(ip), None, ctypes.byref(done),
+                             FAKE, 1 << 40, None)
+        assert st == dwg.DWG_E_INVALID
+        assert done.value == 0
+
+
+def test_knn_and_mlp_validation():
+    lib = dwg.load()
+    assert lib.dwg_knn(FAKE, 100, FAKE, 100, 0, 17, FAKE, None, FAKE, 1 << 40, None) == dwg.DWG_E_INVALID
+    assert lib.dwg_knn(FAKE, 5, FAKE, 100, 1, 5, FAKE, None, FAKE, 1 << 40, None) == dwg.DWG_E_INVALID
+    assert lib.dwg_delta_knn_mean(FAKE, 100, 10, 0.0, FAKE, FAKE, 1 << 40, None) == dwg.DWG_E_INVALID
+    assert lib.dwg_mlp_train_step(FAKE, FAKE, FAKE, 0, 1e-3, FAKE, FAKE, None, 10, None, None, FAKE, 1 << 40,
+                                  None) == dwg.DWG_E_INVALID
+    assert lib.dwg_init_normals(7, 0, None, 10, None, FAKE, None, 0, None) == dwg.DWG_E_INVALID
+    assert dwg.mlp_param_count() == 128 * 48 + 128 + 128 * 128 + 128 + 3 * 128 + 3
+
+
+def test_single_hip_runtime_in_process():
+    """libdwg must bind to the HIP runtime torch already loaded (one libamdhip64 mapped)."""
+    dwg.load()
+    maps = open("/proc/self/maps").read()
+    paths = {line.split()[-1] for line in maps.splitlines() if "libamdhip64" in line}
+    assert len(paths) == 1, paths

@@ -1,0 +1,133 @@
+"""GPU parity of the DWG iteration (update, iso-value, convergence statistic), of the random
+initial normals and of the kNN radius against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2405_13839_amd import synth
+from tests.helpers import angle_deg, cuda, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _dwg():
+    from paper_2405_13839_amd import dwg
+    return dwg
+
+
+def test_random_normals_match_counter_rng():
+    dwg = _dwg()
+    for n, seed in [(1, 0), (1000, 200), (100_003, 2**63 + 5)]:
+        N = host(dwg.random_normals(n, seed, "cuda"))
+        ref = oracle.random_normals(seed, n)
+        assert np.max(np.abs(N - ref)) <= 2e-6
+        np.testing.assert_allclose(np.linalg.norm(N.astype(np.float64), axis=0), 1.0, atol=3e-7)
+
+
+def _c1(n=2000, seed=100):
+    c = synth.sphere(n, 0.005, seed)
+    delta = (2.0 * oracle.delta(c.P, 10)).astype(np.float32)
+    N0 = oracle.random_normals(200, n).astype(np.float32)
+    return c, delta, N0
+
+
+@pytest.mark.parametrize("lam", [0.0, 10.0])
+def test_one_iteration_matches_oracle(lam):
+    dwg = _dwg()
+    c, delta, N0 = _c1()
+    Ng = cuda(N0)
+    st, stats = dwg.iterate(cuda(c.P), cuda(c.area), cuda(delta), Ng, dwg.Params(lam=lam), max_iters=1,
+                            fixed_iters=True)
+    assert st == dwg.DWG_OK
+    N1, ost = oracle.dwg_run(c.P, c.area, delta, N0, lam=lam, max_iters=1)
+    ang = angle_deg(host(Ng), N1)
+    assert ang.max() < 1e-3
+    s = stats.numpy()[0]
+    assert abs(s[0] - ost[0, 0]) <= 1e-5 * max(1, abs(ost[0, 0]))
+    assert abs(s[1] - ost[0, 1]) <= 1e-3
+    assert abs(s[2] - ost[0, 2]) <= 1e-5 * ost[0, 2]
+
+
+def test_c1_trajectory_matches_oracle():
+    """Plain DWG, 2,000 noisy sphere points, 30 fixed iterations from the same random normals:
+    GPU (FP32) and oracle (FP64) end with the same orientation at >= 99.9% of the points, and
+    both agree with the analytic normals up to one global sign."""
+    dwg = _dwg()
+    c, delta, N0 = _c1()
+    Ng = cuda(N0)
+    st, stats = dwg.iterate(cuda(c.P), cuda(c.area), cuda(delta), Ng, dwg.Params(), max_iters=30, fixed_iters=True)
+    Nr, ost = oracle.dwg_run(c.P, c.area, delta, N0, max_iters=30)
+    Ng = host(Ng).astype(np.float64)
+    agree = np.mean(np.sum(Ng * Nr, axis=0) > 0)
+    assert agree >= 0.999
+    np.testing.assert_allclose(stats.numpy()[:, 0], ost[:, 0], rtol=1e-3, atol=1e-4)
+    cos_t = np.sum(Ng * c.N_true, axis=0)
+    assert max(np.mean(cos_t > 0), np.mean(cos_t < 0)) >= 0.999
+
+
+def test_status_codes_and_resume():
+    dwg = _dwg()
+    c, delta, N0 = _c1(1500, 3)
+    P, a, d = cuda(c.P), cuda(c.area), cuda(delta)
+    # resume: 7 + 5 fixed iterations equal 12, bitwise (the state is just the normals)
+    Na, Nb = cuda(N0), cuda(N0)
+    dwg.iterate(P, a, d, Na, max_iters=12, fixed_iters=True)
+    dwg.iterate(P, a, d, Nb, max_iters=7, fixed_iters=True)
+    dwg.iterate(P, a, d, Nb, max_iters=5, fixed_iters=True)
+    assert torch.equal(Na, Nb)
+    # not converged after 1 iteration from random normals
+    Nc = cuda(N0)
+    st, stats = dwg.iterate(P, a, d, Nc, max_iters=1, fixed_iters=False)
+    assert st == dwg.DWG_NOT_CONVERGED and stats.shape[0] == 1
+    # converged normals: a further run stops at once with a small statistic
+    st, stats = dwg.iterate(P, a, d, Na, max_iters=100, fixed_iters=False)
+    assert st == dwg.DWG_OK and stats[-1, 1] <= 0.1
+    # NaN input -> DWG_E_NONFINITE, normals stay finite
+    bad = c.area.copy()
+    bad[5] = np.nan
+    Nd = cuda(N0)
+    with pytest.raises(dwg.DwgError) as ei:
+        dwg.iterate(P, cuda(bad), d, Nd, max_iters=3)
+    assert ei.value.status == dwg.DWG_E_NONFINITE
+    assert torch.isfinite(Nd).all()
+
+
+def test_top_fraction_statistic_exact():
+    """The convergence statistic is the exact mean of the ceil(top_frac n) largest angle
+    changes: check it against a sort of the angles the GPU produced."""
+    dwg = _dwg()
+    c, delta, N0 = _c1(3001, 8)
+    Ng = cuda(N0)
+    for frac in [0.01, 0.2, 1.0]:
+        N_old = host(Ng).astype(np.float64)
+        st, stats = dwg.iterate(cuda(c.P), cuda(c.area), cuda(delta), Ng, max_iters=1, fixed_iters=True,
+                                top_frac=frac)
+        N_new = host(Ng).astype(np.float64)
+        ch = np.linalg.norm(N_new - N_old, axis=0)
+        th = np.degrees(2 * np.arcsin(np.minimum(1, ch / 2)))
+        k = dwg.top_count(N_old.shape[1], frac)
+        assert k == oracle.top_count(N_old.shape[1], frac)
+        np.testing.assert_allclose(stats[0, 1].item(), np.sort(th)[::-1][:k].mean(), rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(stats[0, 2].item(), ch.mean(), rtol=1e-12)
+
+
+@pytest.mark.parametrize("n,k", [(17, 16), (2000, 10), (50_000, 16)])
+def test_knn_and_delta_match_oracle(n, k):
+    dwg = _dwg()
+    c = synth.torus_ellipsoids(max(n, 64), seed=31)
+    P = c.P[:, :n].copy()
+    Pc = cuda(P)
+    idx, dist = dwg.knn(Pc, Pc, k, self_skip=True)
+    idx, dist = host(idx), host(dist).astype(np.float64)
+    sel = np.arange(n) if n <= 5000 else np.random.default_rng(0).choice(n, 3000, replace=False)
+    ridx, rdist = oracle.knn(P, P[:, sel], k, skip=sel)
+    # distances (unique) agree; indices are valid neighbours at the distance they claim
+    np.testing.assert_allclose(dist[sel], rdist, rtol=2e-6, atol=1e-7)
+    assert np.all(idx[sel] != sel[:, None])
+    true_d = np.linalg.norm(P[:, idx[sel]].astype(np.float64) - P[:, sel][:, :, None].astype(np.float64), axis=0)
+    np.testing.assert_allclose(true_d, rdist, rtol=2e-6, atol=1e-7)
+    for row in idx[sel]:
+        assert len(set(row.tolist())) == k
+    delta = host(dwg.delta_knn_mean(Pc, k))
+    np.testing.assert_allclose(delta[sel], rdist.mean(axis=1), rtol=3e-6)
