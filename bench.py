@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Benchmark of the DWG hot path on one MI355X.
+
+Workload (default): 1,000,000 points on a torus (R=1, r=0.3) united with 2 random
+ellipsoids (semi-axes U[0.2,0.6]), 5% uniform outliers, Gaussian noise 0.25% of the
+bounding-box diagonal, area weights = visible area / inliers, screened kernel lambda=10,
+kernel radius = 2 x mean 10-NN distance. Seeded synthetic data (the paper's scanned models
+are not available); see synth.torus_ellipsoids.
+
+One step = one complete orientation solve with the inputs resident in HBM: kNN radius,
+initial normals (learned MLP init when its weights exist, else random), then DWG
+iterations (all-pairs screened GWN + gradient, normal update, FP64 iso-value and top-1%
+convergence statistic) until the convergence test passes or --max-iters.
+
+value = pair interactions evaluated / second over the timed steps (whole job).
+Prints one JSON line (rank 0, N = 1 GPU only).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+FLOP_PER_PAIR = {False: 32, True: 44}  # algorithmic FLOP per (query, source) pair with gradient
+FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (256 CU x 2.4 GHz x 256 FLOP/clk)
+WEIGHTS = os.path.join(ROOT, "paper_2405_13839_amd", "weights", "mlp_init.safetensors")
+TRAFFIC = os.path.join(ROOT, "profiles", "gwn_traffic.json")
+GWN_SRC = os.path.join(ROOT, "paper_2405_13839_amd", "csrc", "dwg_gwn.hip")
+
+
+def kernel_sha() -> str:
+    return hashlib.sha256(open(GWN_SRC, "rb").read()).hexdigest()[:16]
+
+
+def traffic_per_launch(n: int):
+    """HBM bytes per launch of the all-pairs kernel from the committed rocprofv3 PMC summary,
+    or None when it was taken on another kernel source or size."""
+    try:
+        t = json.load(open(TRAFFIC))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_src_sha") != kernel_sha() or int(t.get("n", -1)) != n:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--lam", type=float, default=10.0)
+    ap.add_argument("--init", choices=["auto", "mlp", "random"], default="auto")
+    ap.add_argument("--max-iters", type=int, default=30)
+    ap.add_argument("--compare-iters", type=int, default=20,
+                    help="iteration cap of the one untimed random-init comparison solve (0 = skip)")
+    ap.add_argument("--cpu-queries", type=int, default=4096,
+                    help="queries of the oracle CPU-baseline sample (0 = skip)")
+    ap.add_argument("--seed", type=int, default=102)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding of the "
+              "path is a design note, not implemented", file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+
+    from paper_2405_13839_amd import dwg, metrics, synth
+
+    dev = torch.device("cuda", int(os.environ.get("LOCAL_RANK", 0)))
+    torch.cuda.set_device(dev)
+    init = args.init
+    if init == "auto":
+        init = "mlp" if os.path.exists(WEIGHTS) else "random"
+
+    cloud = synth.torus_ellipsoids(args.n, seed=args.seed)
+    n = cloud.n
+    P = torch.from_numpy(cloud.P).to(dev)
+    area = torch.from_numpy(cloud.area).to(dev)
+    prm = dwg.Params(lam=args.lam)
+    ws = dwg.workspace(n, n, dev, prm)
+    mlp = None
+    if init == "mlp":
+        from paper_2405_13839_amd import mlp_init
+        mlp = mlp_init.load_params(WEIGHTS, dev)
+
+    def solve(kind, max_iters, seed=202):
+        delta = dwg.delta_knn_mean(P, 10, 2.0, ws=ws)
+        if kind == "mlp":
+            N = dwg.mlp_normals(P, mlp, ws=ws)
+        else:
+            N = dwg.random_normals(n, seed, dev)
+        st, stats = dwg.iterate(P, area, delta, N, prm, max_iters=max_iters, eps_deg=0.1, ws=ws)
+        return N, st, stats
+
+    for _ in range(args.warmup):
+        solve(init, args.max_iters)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = []
+    for _ in range(args.steps):
+        runs.append(solve(init, args.max_iters))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    iters = [int(r[2].shape[0]) for r in runs]
+    pairs = float(sum(iters)) * n * n
+    value = pairs / dt
+    gwn_ms = float(np.mean(np.concatenate([r[2][:, 3].numpy() for r in runs])))
+    screened = args.lam > 0
+    fl = FLOP_PER_PAIR[screened]
+    achieved = n * n * fl / (gwn_ms * 1e-3) / 1e12
+    rep = metrics.orientation_report(runs[-1][0].cpu().numpy(), cloud.N_true, cloud.comp)
+    last = runs[-1][2][-1].numpy()
+
+    result = {
+        "metric": "GWN+grad pair-interactions/s (% FP32 peak); time-to-converged normals @1M pts",
+        "value": value,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"torus R=1 r=0.3 + 2 ellipsoids, {n} points (5% outliers, noise 0.25% diag), "
+                        f"screened lambda={args.lam}, radius 2x mean 10-NN, {init} init, solve to "
+                        f"top-1% mean change <= 0.1 deg (cap {args.max_iters})",
+            "n_points": n,
+            "lambda": args.lam,
+            "init": init,
+            "parallelism": "single GPU",
+        },
+        "pct_fp32_peak_alg": 100.0 * value * fl / (FP32_PEAK_TFLOPS * 1e12),
+        "time_to_converged_s": dt / args.steps,
+        "iterations": iters,
+        "converged": [int(r[1]) == dwg.DWG_OK for r in runs],
+        "final_top1pct_deg": float(last[1]),
+        "orientation": rep,
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP32_PEAK_TFLOPS,
+            "traffic": traffic_per_launch(n),
+        },
+        "gwn_kernel_ms": gwn_ms,
+    }
+
+    if args.compare_iters > 0 and init != "random":
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        Nr, str_, sr = solve("random", args.compare_iters)
+        torch.cuda.synchronize()
+        rr = metrics.orientation_report(Nr.cpu().numpy(), cloud.N_true, cloud.comp)
+        result["random_init"] = {"seconds": time.perf_counter() - t1, "iterations": int(sr.shape[0]),
+                                 "converged": int(str_) == dwg.DWG_OK, "orientation": rr}
+
+    if args.cpu_queries > 0:
+        import oracle
+        rng = np.random.default_rng(7)
+        sel = np.sort(rng.choice(n, min(args.cpu_queries, n), replace=False))
+        Nh = runs[-1][0].cpu().numpy()
+        dh = dwg.delta_knn_mean(P, 10, 2.0, ws=ws).cpu().numpy()
+        oracle.num_threads()
+        t2 = time.perf_counter()
+        oracle.gwn(cloud.P, Nh, cloud.area, dh, cloud.P[:, sel], lam=args.lam)
+        ct = time.perf_counter() - t2
+        result["cpu_baseline"] = {
+            "value": len(sel) * n / ct,
+            "unit": "pair-interactions/s",
+            "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{len(sel)} random queries x {n} sources, same screened kernel, FP64 "
+                      f"({ct:.1f} s); per-iteration time extrapolates to {n * n / (len(sel) * n / ct):.0f} s",
+        }
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -63,6 +63,8 @@ typedef struct dwg_iter_stat {
   double wmean;        /* Eq. 6: mean GWN over the input points (the iso-value) */
   double top_mean_deg; /* mean of the ceil(top_frac*n) largest angle changes (deg) */
   double mean_chord;   /* (1/n) sum |n_i^(t) - n_i^(t-1)| */
+  double gwn_ms;       /* duration of this iteration's all-pairs kernel (HIP events on the
+                          caller's stream), milliseconds */
 } dwg_iter_stat;
 
 typedef enum dwg_init_kind { DWG_INIT_RANDOM = 0, DWG_INIT_MLP = 1 } dwg_init_kind;

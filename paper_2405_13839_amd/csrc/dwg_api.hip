@@ -80,6 +80,20 @@ size_t aux_bytes(int64_t n) {
   return c.used + knn_ws_bytes(n, n);
 }
 
+// Two HIP events, destroyed with the object.
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  dwg_status create() {
+    DWG_TRY_HIP(hipEventCreate(&a));
+    DWG_TRY_HIP(hipEventCreate(&b));
+    return DWG_OK;
+  }
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
 size_t gwn_bytes(int64_t n_src, int64_t n_qry, const dwg_kernel_params& kp) {
   Carver c(nullptr);
   carve_gwn(c, n_src, n_qry, choose_split(n_src, n_qry, kp.split), nullptr);
@@ -182,18 +196,25 @@ dwg_status dwg_iterate(const float* P, const float* area, const float* delta, in
   GwnWork wk;
   carve_gwn(c, n, n, choose_split(n, n, kp.split), &wk);
   DWG_PROPAGATE(launch_stage(P, N_inout, area, delta, n, kp.eps, wk, st));
+  EventPair ev;
+  DWG_PROPAGATE(ev.create());
   dwg_status result = DWG_NOT_CONVERGED;
   for (int t = 0; t < ip->max_iters; ++t) {
+    DWG_TRY_HIP(hipEventRecord(ev.a, st));
     DWG_PROPAGATE(launch_gwn(P, n, kp, true, wk, st));
+    DWG_TRY_HIP(hipEventRecord(ev.b, st));
     DWG_PROPAGATE(launch_update(n, area, kp, N_inout, wk, st));
     DWG_PROPAGATE(launch_stats(n, ip->top_frac, wk, st));
     double hs[4];
     DWG_TRY_HIP(hipMemcpyAsync(hs, wk.stats, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
     DWG_TRY_HIP(hipStreamSynchronize(st));
+    float kms = 0.0f;
+    DWG_TRY_HIP(hipEventElapsedTime(&kms, ev.a, ev.b));
     if (stats_host) {
       stats_host[t].wmean = hs[0];
       stats_host[t].top_mean_deg = hs[1];
       stats_host[t].mean_chord = hs[2];
+      stats_host[t].gwn_ms = (double)kms;
     }
     if (iters_done) *iters_done = t + 1;
     if (!std::isfinite(hs[0]) || !std::isfinite(hs[1]) || !std::isfinite(hs[2])) {

@@ -40,7 +40,8 @@ class IterateParams(ctypes.Structure):
 
 
 class IterStat(ctypes.Structure):
-    _fields_ = [("wmean", ctypes.c_double), ("top_mean_deg", ctypes.c_double), ("mean_chord", ctypes.c_double)]
+    _fields_ = [("wmean", ctypes.c_double), ("top_mean_deg", ctypes.c_double), ("mean_chord", ctypes.c_double),
+                ("gwn_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -169,7 +170,8 @@ def gwn(P, N, area, delta, Q, params: Params | None = None, grad=True, ws=None, 
 
 def iterate(P, area, delta, N, params: Params | None = None, max_iters=50, fixed_iters=False, eps_deg=0.1,
             top_frac=0.01, ws=None):
-    """Run Algorithm 1 in place on N ([3, n] float32). Returns (status, stats float64 [T, 3])."""
+    """Run Algorithm 1 in place on N ([3, n] float32). Returns (status, stats float64 [T, 4]):
+    per iteration wmean, top-1% mean angle change (deg), mean chord, all-pairs kernel ms."""
     lib = load()
     params = params or Params()
     P = _dev(P, "P")
@@ -188,7 +190,8 @@ def iterate(P, area, delta, N, params: Params | None = None, max_iters=50, fixed
     st = lib.dwg_iterate(_ptr(P), _ptr(area), _ptr(delta), n, _ptr(N), ctypes.byref(kp), ctypes.byref(ip), stats,
                          ctypes.byref(done), _ptr(ws), ws.numel(), _stream(dev))
     _check(st, ok=(DWG_OK, DWG_NOT_CONVERGED))
-    out = torch.tensor([[s.wmean, s.top_mean_deg, s.mean_chord] for s in stats[: done.value]], dtype=torch.float64)
+    out = torch.tensor([[s.wmean, s.top_mean_deg, s.mean_chord, s.gwn_ms] for s in stats[: done.value]],
+                       dtype=torch.float64).reshape(-1, 4)
     return st, out
 
 

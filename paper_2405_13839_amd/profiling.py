@@ -1,0 +1,57 @@
+"""Small fixed workloads to run under rocprofv3 (kernel trace and PMC counters).
+
+    python -m paper_2405_13839_amd.profiling gwn  --n 1000000 --lam 10 --reps 2
+    python -m paper_2405_13839_amd.profiling copy --mib 1024 --reps 3
+
+`gwn` launches the all-pairs kernel through dwg_gwn_grad on the C3 workload shape; `copy`
+runs a plain device-to-device copy of a known size, used to calibrate the FETCH_SIZE /
+WRITE_SIZE counters (bytes the counters report per byte actually moved).
+"""
+from __future__ import annotations
+
+import argparse
+import sys
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("what", choices=["gwn", "copy", "iterate"])
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--lam", type=float, default=10.0)
+    ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--mib", type=int, default=1024)
+    args = ap.parse_args(argv)
+    import numpy as np
+    import torch
+
+    dev = torch.device("cuda", 0)
+    if args.what == "copy":
+        x = torch.ones(args.mib * 262144, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(args.reps):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(f"copied {args.mib} MiB x {args.reps}")
+        return 0
+    from paper_2405_13839_amd import dwg, synth
+
+    c = synth.torus_ellipsoids(args.n, seed=102)
+    P = torch.from_numpy(c.P).to(dev)
+    a = torch.from_numpy(c.area).to(dev)
+    prm = dwg.Params(lam=args.lam)
+    ws = dwg.workspace(c.n, c.n, dev, prm)
+    d = dwg.delta_knn_mean(P, 10, 2.0, ws=ws)
+    N = dwg.random_normals(c.n, 202, dev)
+    if args.what == "gwn":
+        for _ in range(args.reps):
+            dwg.gwn(P, N, a, d, P, prm, ws=ws)
+        torch.cuda.synchronize()
+    else:
+        st, stats = dwg.iterate(P, a, d, N, prm, max_iters=args.reps, fixed_iters=True, ws=ws)
+        print("kernel ms per iteration:", np.round(stats[:, 3].numpy(), 3).tolist())
+    print(f"{args.what}: n={c.n} lam={args.lam} reps={args.reps} done")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
