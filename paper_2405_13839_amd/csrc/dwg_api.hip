@@ -72,12 +72,17 @@ dwg_status check_device() {
 
 // kNN-based stages (delta radius, anchor features): neighbour lists of n queries with up to
 // 16 neighbours, the anchor copy and the grid.
+int64_t feat_chunk(int64_t n) { return std::min<int64_t>(n, int64_t(1) << 20); }
+
 size_t aux_bytes(int64_t n) {
   Carver c(nullptr);
   c.take<float>(3 * (size_t)n);
   c.take<int32_t>((size_t)n * kMaxK);
   c.take<float>((size_t)n * kMaxK);
-  return c.used + knn_ws_bytes(n, n);
+  const size_t knn = c.used + knn_ws_bytes(n, n);
+  Carver a(nullptr);
+  carve_anchor(a, n, n, DWG_FEAT_ANCHORS, nullptr);
+  return std::max(knn, a.used);
 }
 
 // Two HIP events, destroyed with the object.
@@ -96,7 +101,7 @@ struct EventPair {
 
 size_t gwn_bytes(int64_t n_src, int64_t n_qry, const dwg_kernel_params& kp) {
   Carver c(nullptr);
-  carve_gwn(c, n_src, n_qry, choose_split(n_src, n_qry, kp.split), nullptr);
+  carve_gwn(c, n_src, n_qry, choose_split(n_src, n_qry, kp.split), false, nullptr);
   return c.used;
 }
 
@@ -120,7 +125,9 @@ dwg_status gwn_common(const float* P, const float* N, const float* area, const f
   hipStream_t st = static_cast<hipStream_t>(stream);
   Carver c(ws);
   GwnWork wk;
-  carve_gwn(c, n, m, choose_split(n, m, kp.split), &wk);
+  const bool same = (Q == P && m == n);
+  carve_gwn(c, n, m, choose_split(n, m, kp.split), same, &wk);
+  DWG_PROPAGATE(launch_order(P, n, delta, kp.eps, Q, m, same, wk, st));
   DWG_PROPAGATE(launch_stage(P, N, area, delta, n, kp.eps, wk, st));
   DWG_PROPAGATE(launch_gwn(Q, m, kp, grad, wk, st));
   DWG_PROPAGATE(launch_combine(m, kp, grad, w, g, wmean, wk, st));
@@ -194,7 +201,8 @@ dwg_status dwg_iterate(const float* P, const float* area, const float* delta, in
   hipStream_t st = static_cast<hipStream_t>(stream);
   Carver c(ws);
   GwnWork wk;
-  carve_gwn(c, n, n, choose_split(n, n, kp.split), &wk);
+  carve_gwn(c, n, n, choose_split(n, n, kp.split), true, &wk);
+  DWG_PROPAGATE(launch_order(P, n, delta, kp.eps, P, n, true, wk, st));
   DWG_PROPAGATE(launch_stage(P, N_inout, area, delta, n, kp.eps, wk, st));
   EventPair ev;
   DWG_PROPAGATE(ev.create());
@@ -203,7 +211,7 @@ dwg_status dwg_iterate(const float* P, const float* area, const float* delta, in
     DWG_TRY_HIP(hipEventRecord(ev.a, st));
     DWG_PROPAGATE(launch_gwn(P, n, kp, true, wk, st));
     DWG_TRY_HIP(hipEventRecord(ev.b, st));
-    DWG_PROPAGATE(launch_update(n, area, kp, N_inout, wk, st));
+    DWG_PROPAGATE(launch_update(n, kp, N_inout, wk, st));
     DWG_PROPAGATE(launch_stats(n, ip->top_frac, wk, st));
     double hs[4];
     DWG_TRY_HIP(hipMemcpyAsync(hs, wk.stats, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -246,26 +254,25 @@ dwg_status dwg_init_normals(dwg_init_kind kind, uint64_t seed, const float* P, i
   }
   DWG_CHECK(P && mlp_params, "P and mlp_params must not be NULL for DWG_INIT_MLP");
   DWG_CHECK(n >= DWG_FEAT_K + 2, "DWG_INIT_MLP needs at least %d points", DWG_FEAT_K + 2);
-  const size_t need = dwg_workspace_bytes(n, n, nullptr);
+  const size_t need = aux_bytes(n);
   DWG_CHECK(ws || ws_bytes == 0, "ws is NULL but ws_bytes > 0");
   if (!ws || ws_bytes < need) {
     set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
     return DWG_E_WORKSPACE;
   }
   DWG_PROPAGATE(check_device());
-  // Features and MLP in chunks so that the [chunk][48] feature buffer stays bounded.
+  // anchors and their grid once, then features and the MLP in chunks of <= 2^20 points,
+  // written straight into the planar [3][n] output
   Carver c(ws);
-  const int64_t chunk = std::min<int64_t>(n, 1 << 20);
-  float* feat = c.take<float>((size_t)chunk * DWG_MLP_IN);
-  float* y = c.take<float>((size_t)chunk * 3);
-  void* rest = static_cast<char*>(ws) + c.used;
-  const size_t rest_bytes = ws_bytes - c.used;
-  (void)feat;
-  (void)y;
-  (void)rest;
-  (void)rest_bytes;
-  set_error("DWG_INIT_MLP: not available in this build");
-  return DWG_E_UNSUPPORTED;
+  AnchorCtx x;
+  carve_anchor(c, n, feat_chunk(n), DWG_FEAT_ANCHORS, &x);
+  DWG_PROPAGATE(anchor_build(P, n, x, st));
+  for (int64_t q0 = 0; q0 < n; q0 += x.chunk) {
+    const int64_t cnt = std::min<int64_t>(x.chunk, n - q0);
+    DWG_PROPAGATE(anchor_features(P, n, q0, cnt, x, x.feat, st));
+    DWG_PROPAGATE(mlp_forward(mlp_params, x.feat, cnt, N_out + q0, 1, n, st));
+  }
+  return DWG_OK;
 }
 
 dwg_status dwg_knn(const float* R, int64_t nr, const float* Q, int64_t m, int self_skip, int k,

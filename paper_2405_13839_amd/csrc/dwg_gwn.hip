@@ -1,14 +1,17 @@
 // All-pairs GWN / gradient kernels, the normal-update epilogue and the FP64 statistics of
 // one DWG iteration (Sec. 3 Eq. 2-3, Sec. 4.2 Eq. 5, Sec. 4.3 Eq. 6-7, Sec. 5.1-5.2).
 //
-// Data layout in HBM (all carved from the caller's workspace):
-//   src   [2*npad] float4  per source j: (p_j, 1/max(delta_j, eps)), (m_j, 0) with
+// Data layout in HBM (all carved from the caller's workspace; "sorted" = the spatial order
+// of dwg_sort.hip, perm[i] = original index of sorted position i):
+//   src   [2*npad] float4  sorted sources: (p_j, 1/max(delta_j, eps)), (m_j, 0) with
 //                          m_j = a_j n_j / (4 pi); padding sources are all zero, which makes
-//                          their contribution exactly zero (see pair_* below).
-//   part  [split][7][mpad] per-split partial sums of w, A = sum t d, B = sum rho^-3 m.
-//   kk    [npad]           a_j / (4 pi) (restaging after the update)
-//   theta [m] double       angle between consecutive normals, degrees.
-// Queries are read straight from the caller's planar [3][m] array.
+//                          their contribution exactly zero in the general path.
+//   kk    [npad]           a_j / (4 pi) per sorted source (restaging after the update)
+//   tbox  [2*ntiles]       per source tile: (min xyz, max radius), (max xyz, 0)
+//   qbox  [2*nqblk]        per block of 1024 sorted queries: (min xyz, 0), (max xyz, 0)
+//   part  [split][7][mpad] per-split partial sums of w, A, B per sorted query
+//   theta [m] double       angle between consecutive normals (degrees), sorted order
+// Queries are gathered from the caller's planar [3][m] array through the query permutation.
 #include <cmath>
 
 #include "dwg_internal.h"
@@ -20,8 +23,8 @@ constexpr float kInv4Pi = 0.0795774715459476678844f;
 // 2^126: r2 * kCoincide is 0 exactly when r2 == 0 and larger than 1/r for every pair with
 // r2 >= 2^-84; it is the third operand of the min that zeroes coincident pairs.
 constexpr float kCoincide = 8.507059173023462e37f;
-// Added to r2 before rsqrt in the screened kernel so that r = r2 * rsqrt(r2 + tiny) is 0
-// (not 0 * inf) for coincident pairs; below half an ulp of any r2 >= 2^-84.
+// Added to r2 before rsqrt in the general screened path so that r = r2 * rsqrt(r2 + tiny) is
+// 0 (not 0 * inf) for coincident pairs; below half an ulp of any r2 >= 2^-84.
 constexpr float kTiny = 1e-37f;
 constexpr double kRadToDeg = 57.295779513082320876798;
 
@@ -35,16 +38,24 @@ __device__ __forceinline__ float min3_nonneg(float a, float b, float c) {
   return __uint_as_float(min(min(x, y), z));
 }
 
+// Per-pair constants of the screened kernel.
+struct Scr {
+  float s3;           // 3 s
+  float neg_s_log2e;  // -s log2(e)
+  float s2;           // s^2
+};
+
 // One (query, source) pair of the plain kernel (Eq. 2-3 with the modified Poisson kernel).
 //   ip = 1/rho = min(1/r, 1/max(delta,eps)), and 0 when r == 0 (pair skipped).
 //   w += c ip^3;  B += ip^3 m;  A += [rho == r] c ip^5 d;  grad = 3 A - B.
-template <bool GRAD>
+// FAR: the caller guarantees r > max(delta_j, eps) > = 0 and r > 0, so ip = 1/r.
+template <bool GRAD, bool FAR>
 __device__ __forceinline__ void pair_plain(const float4 a, const float4 b, float qx, float qy,
                                            float qz, float* acc) {
   const float dx = a.x - qx, dy = a.y - qy, dz = a.z - qz;
   const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
   const float ir = rsq(r2);
-  const float ip = min3_nonneg(ir, a.w, r2 * kCoincide);
+  const float ip = FAR ? ir : min3_nonneg(ir, a.w, r2 * kCoincide);
   const float ip2 = ip * ip;
   const float ip3 = ip2 * ip;
   const float c = fmaf(dz, b.z, fmaf(dy, b.y, dx * b.x));
@@ -56,55 +67,77 @@ __device__ __forceinline__ void pair_plain(const float4 a, const float4 b, float
     acc[4] = fmaf(ip3, b.x, acc[4]);
     acc[5] = fmaf(ip3, b.y, acc[5]);
     acc[6] = fmaf(ip3, b.z, acc[6]);
-    const float t = (ir <= a.w) ? e * ip2 : 0.0f;
+    const float t = (FAR || ir <= a.w) ? e * ip2 : 0.0f;
     acc[1] = fmaf(t, dx, acc[1]);
     acc[2] = fmaf(t, dy, acc[2]);
     acc[3] = fmaf(t, dz, acc[3]);
   }
 }
 
-// One pair of the screened kernel (Eq. 5): E = e^{-s r}, phi = E (1 + s r).
-//   w += c phi ip^3;  B += phi ip^3 m;
-//   A += c E ip^3 (3 (1 + s r) ip^2 [rho == r] + s^2) d;  grad = A - B.
-template <bool GRAD>
+// One pair of the screened kernel (Eq. 5): E = e^{-s r}, o3 = 3 (1 + s r), f = E ip^3.
+//   w' += c f o3            (= 3 w)
+//   B' += f o3 m            (= 3 B with B = sum phi ip^3 m)
+//   A  += c f (o3 ip^2 [rho == r] + s^2) d
+//   grad = A - B' / 3,  w = w' / 3.
+template <bool GRAD, bool FAR>
 __device__ __forceinline__ void pair_screened(const float4 a, const float4 b, float qx, float qy,
-                                              float qz, float s, float neg_s_log2e, float s2,
-                                              float* acc) {
+                                              float qz, const Scr k, float* acc) {
   const float dx = a.x - qx, dy = a.y - qy, dz = a.z - qz;
   const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-  const float ir = rsq(r2 + kTiny);
-  const float ip = min3_nonneg(ir, a.w, r2 * kCoincide);
+  const float ir = rsq(FAR ? r2 : r2 + kTiny);
+  const float ip = FAR ? ir : min3_nonneg(ir, a.w, r2 * kCoincide);
   const float ip2 = ip * ip;
   const float ip3 = ip2 * ip;
   const float r = r2 * ir;
-  const float E = exp2_hw(r * neg_s_log2e);
-  const float onesr = fmaf(s, r, 1.0f);
+  const float E = exp2_hw(r * k.neg_s_log2e);
+  const float o3 = fmaf(k.s3, r, 3.0f);
   const float f = E * ip3;
   const float c = fmaf(dz, b.z, fmaf(dy, b.y, dx * b.x));
   const float e0 = c * f;
-  acc[0] = fmaf(e0, onesr, acc[0]);
+  acc[0] = fmaf(e0, o3, acc[0]);
   if (GRAD) {
-    const float g = f * onesr;
+    const float g = f * o3;
     acc[4] = fmaf(g, b.x, acc[4]);
     acc[5] = fmaf(g, b.y, acc[5]);
     acc[6] = fmaf(g, b.z, acc[6]);
-    const float h = fmaf(3.0f * onesr, ip2, s2);
-    const float t = e0 * ((ir <= a.w) ? h : s2);
+    const float h = fmaf(o3, ip2, k.s2);
+    const float t = e0 * ((FAR || ir <= a.w) ? h : k.s2);
     acc[1] = fmaf(t, dx, acc[1]);
     acc[2] = fmaf(t, dy, acc[2]);
     acc[3] = fmaf(t, dz, acc[3]);
   }
 }
 
-// All-pairs kernel. Block = 256 threads holding QPT queries each (query q0 + k*256 + tid);
-// grid.y = source split. Source tiles of 256 are staged in LDS and read back as broadcasts.
-// Each tile's contributions go to FP32 partials, which are then folded into running sums
-// (Kahan-compensated when KAHAN).
+template <int QPT, int NA, bool GRAD, bool SCREENED, bool FAR>
+__device__ __forceinline__ void tile_loop(const float4* sa, const float4* sb, const float* qx, const float* qy,
+                                          const float* qz, const Scr k, float (*acc)[NA]) {
+#pragma unroll 2
+  for (int j = 0; j < kTile; ++j) {
+    const float4 a = sa[j];
+    const float4 b = sb[j];
+#pragma unroll
+    for (int q = 0; q < QPT; ++q) {
+      if (SCREENED)
+        pair_screened<GRAD, FAR>(a, b, qx[q], qy[q], qz[q], k, acc[q]);
+      else
+        pair_plain<GRAD, FAR>(a, b, qx[q], qy[q], qz[q], acc[q]);
+    }
+  }
+}
+
+// All-pairs kernel. Block = 256 threads holding QPT queries each (sorted query
+// q0 + k*256 + tid); grid.y = source split. Source tiles of 256 are staged in LDS and read
+// back as broadcasts. Per tile, the block decides (uniformly) whether the tile is far from
+// all of its queries -- box distance above the tile's largest radius, so no pair can be
+// clamped or coincident -- and then runs the shorter far-pair loop. Each tile's contributions
+// go to FP32 partials, folded into running sums (Kahan-compensated when KAHAN).
 template <int QPT, bool GRAD, bool SCREENED, bool KAHAN>
 __global__ __launch_bounds__(kBlock) void k_gwn(const float* __restrict__ Q, int64_t m,
+                                                 const int32_t* __restrict__ qperm,
                                                  const float4* __restrict__ src, int64_t ntiles,
-                                                 int64_t tiles_per_split, float s,
-                                                 float neg_s_log2e, float s2,
+                                                 int64_t nfull, int64_t tiles_per_split,
+                                                 const float4* __restrict__ tbox,
+                                                 const float4* __restrict__ qbox, Scr sk,
                                                  float* __restrict__ part, int64_t mpad) {
   constexpr int NA = GRAD ? kNAcc : 1;
   __shared__ float4 sa[kTile];
@@ -116,10 +149,12 @@ __global__ __launch_bounds__(kBlock) void k_gwn(const float* __restrict__ Q, int
   for (int k = 0; k < QPT; ++k) {
     int64_t qi = q0 + k * kBlock + tid;
     if (qi >= m) qi = m - 1;
-    qx[k] = Q[qi];
-    qy[k] = Q[m + qi];
-    qz[k] = Q[2 * m + qi];
+    const int64_t o = qperm[qi];
+    qx[k] = Q[o];
+    qy[k] = Q[m + o];
+    qz[k] = Q[2 * m + o];
   }
+  const float4 qlo = qbox[2 * blockIdx.x], qhi = qbox[2 * blockIdx.x + 1];
   float sum[QPT][NA], cmp[QPT][NA];
 #pragma unroll
   for (int k = 0; k < QPT; ++k)
@@ -132,24 +167,23 @@ __global__ __launch_bounds__(kBlock) void k_gwn(const float* __restrict__ Q, int
     __syncthreads();
     sa[tid] = src[2 * (t * kTile + tid)];
     sb[tid] = src[2 * (t * kTile + tid) + 1];
+    const float4 tlo = tbox[2 * t], thi = tbox[2 * t + 1];
+    const float gx = fmaxf(0.0f, fmaxf(qlo.x - thi.x, tlo.x - qhi.x));
+    const float gy = fmaxf(0.0f, fmaxf(qlo.y - thi.y, tlo.y - qhi.y));
+    const float gz = fmaxf(0.0f, fmaxf(qlo.z - thi.z, tlo.z - qhi.z));
+    const float gap2 = gx * gx + gy * gy + gz * gz;
+    // tiles with padding (t >= nfull) always take the general path
+    const bool far = t < nfull && gap2 > 0.0f && gap2 > 1.0001f * tlo.w * tlo.w;
     __syncthreads();
     float acc[QPT][NA];
 #pragma unroll
     for (int k = 0; k < QPT; ++k)
 #pragma unroll
       for (int a = 0; a < NA; ++a) acc[k][a] = 0.0f;
-#pragma unroll 2
-    for (int j = 0; j < kTile; ++j) {
-      const float4 a = sa[j];
-      const float4 b = sb[j];
-#pragma unroll
-      for (int k = 0; k < QPT; ++k) {
-        if (SCREENED)
-          pair_screened<GRAD>(a, b, qx[k], qy[k], qz[k], s, neg_s_log2e, s2, acc[k]);
-        else
-          pair_plain<GRAD>(a, b, qx[k], qy[k], qz[k], acc[k]);
-      }
-    }
+    if (far)
+      tile_loop<QPT, NA, GRAD, SCREENED, true>(sa, sb, qx, qy, qz, sk, acc);
+    else
+      tile_loop<QPT, NA, GRAD, SCREENED, false>(sa, sb, qx, qy, qz, sk, acc);
 #pragma unroll
     for (int k = 0; k < QPT; ++k)
 #pragma unroll
@@ -173,36 +207,104 @@ __global__ __launch_bounds__(kBlock) void k_gwn(const float* __restrict__ Q, int
   }
 }
 
-// Stage the sources of one evaluation: (p, 1/max(delta,eps)) and m = a n / (4 pi).
+// Stage the sources in spatial order: (p, 1/max(delta,eps)) and m = a n / (4 pi).
 // A NaN delta poisons the source's m so that the result is NaN as in the definition.
 __global__ void k_stage(const float* __restrict__ P, const float* __restrict__ N,
                         const float* __restrict__ A, const float* __restrict__ D, int64_t n,
-                        int64_t npad, float eps, float4* __restrict__ src,
-                        float* __restrict__ kk) {
+                        int64_t npad, float eps, const int32_t* __restrict__ perm,
+                        float4* __restrict__ src, float* __restrict__ kk) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= npad) return;
   float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = make_float4(0.f, 0.f, 0.f, 0.f);
   float k = 0.0f;
   if (j < n) {
-    const float d = D ? D[j] : 0.0f;
+    const int64_t o = perm[j];
+    const float d = D ? D[o] : 0.0f;
     const float fl = d > eps ? d : eps;
     const float id = fl > 0.0f ? 1.0f / fl : INFINITY;
-    k = A[j] * kInv4Pi;
+    k = A[o] * kInv4Pi;
     if (d != d) k = NAN;
-    a = make_float4(P[j], P[n + j], P[2 * n + j], id);
-    b = make_float4(k * N[j], k * N[n + j], k * N[2 * n + j], 0.0f);
+    a = make_float4(P[o], P[n + o], P[2 * n + o], id);
+    b = make_float4(k * N[o], k * N[n + o], k * N[2 * n + o], 0.0f);
   }
   src[2 * j] = a;
   src[2 * j + 1] = b;
   kk[j] = k;
 }
 
-// Sum of `split` partials of accumulator `a` for query i, in split order.
-__device__ __forceinline__ float combine(const float* part, int split, int64_t mpad, int a, int64_t i,
+// Box of each source tile (real sources only) and its largest radius max(delta, eps).
+__global__ __launch_bounds__(kTile) void k_tile_box(const float4* __restrict__ src, int64_t n,
+                                                    float4* __restrict__ tbox) {
+  __shared__ float lds[7][kTile];
+  const int64_t j = (int64_t)blockIdx.x * kTile + threadIdx.x;
+  float v[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.0f};
+  if (j < n) {
+    const float4 a = src[2 * j];
+    v[0] = v[3] = a.x;
+    v[1] = v[4] = a.y;
+    v[2] = v[5] = a.z;
+    v[6] = 1.0f / a.w;  // radius (0 when 1/radius is +inf)
+    if (!(v[6] == v[6])) v[6] = INFINITY;
+  }
+  for (int d = 0; d < 7; ++d) lds[d][threadIdx.x] = v[d];
+  __syncthreads();
+  for (int s = kTile / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      for (int d = 0; d < 3; ++d) lds[d][threadIdx.x] = fminf(lds[d][threadIdx.x], lds[d][threadIdx.x + s]);
+      for (int d = 3; d < 7; ++d) lds[d][threadIdx.x] = fmaxf(lds[d][threadIdx.x], lds[d][threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    tbox[2 * blockIdx.x] = make_float4(lds[0][0], lds[1][0], lds[2][0], lds[6][0]);
+    tbox[2 * blockIdx.x + 1] = make_float4(lds[3][0], lds[4][0], lds[5][0], 0.0f);
+  }
+}
+
+// Box of each block of kQBlock sorted queries.
+__global__ __launch_bounds__(kBlock) void k_query_box(const float* __restrict__ Q, int64_t m,
+                                                      const int32_t* __restrict__ qperm,
+                                                      float4* __restrict__ qbox) {
+  __shared__ float lds[6][kBlock];
+  float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  for (int k = 0; k < kQpt; ++k) {
+    int64_t qi = (int64_t)blockIdx.x * kQBlock + k * kBlock + threadIdx.x;
+    if (qi >= m) qi = m - 1;  // the kernel evaluates the clamped query there as well
+    const int64_t o = qperm[qi];
+    const float x = Q[o], y = Q[m + o], z = Q[2 * m + o];
+    v[0] = fminf(v[0], x);
+    v[1] = fminf(v[1], y);
+    v[2] = fminf(v[2], z);
+    v[3] = fmaxf(v[3], x);
+    v[4] = fmaxf(v[4], y);
+    v[5] = fmaxf(v[5], z);
+  }
+  for (int d = 0; d < 6; ++d) lds[d][threadIdx.x] = v[d];
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      for (int d = 0; d < 3; ++d) lds[d][threadIdx.x] = fminf(lds[d][threadIdx.x], lds[d][threadIdx.x + s]);
+      for (int d = 3; d < 6; ++d) lds[d][threadIdx.x] = fmaxf(lds[d][threadIdx.x], lds[d][threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    qbox[2 * blockIdx.x] = make_float4(lds[0][0], lds[1][0], lds[2][0], 0.0f);
+    qbox[2 * blockIdx.x + 1] = make_float4(lds[3][0], lds[4][0], lds[5][0], 0.0f);
+  }
+}
+
+__global__ void k_iota(int32_t* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (int32_t)i;
+}
+
+// Sum of `split` partials of accumulator `a` for sorted query i, in split order.
+__device__ __forceinline__ float combine(const float* part, int split, int64_t mpad, int na, int a, int64_t i,
                                          bool kahan) {
   float s = 0.0f, c = 0.0f;
   for (int p = 0; p < split; ++p) {
-    const float x = part[((int64_t)p * kNAcc + a) * mpad + i];
+    const float x = part[((int64_t)p * na + a) * mpad + i];
     if (kahan) {
       const float y = x - c;
       const float t = s + y;
@@ -228,10 +330,19 @@ __device__ double block_sum(double v, double* lds) {
   return r;  // valid on thread 0
 }
 
-// Evaluation epilogue: combine splits; w, grad = (3 or 1) A - B; FP64 block partial of w.
+// Output scaling of the accumulators: w = ws w', grad = as A - bs B'.
+struct Scale {
+  float ws, as, bs;
+};
+Scale scale_of(const dwg_kernel_params& kp) {
+  return kp.lambda > 0.0f ? Scale{1.0f / 3.0f, 1.0f, 1.0f / 3.0f} : Scale{1.0f, 3.0f, 1.0f};
+}
+
+// Evaluation epilogue: combine splits; write w and grad at the query's original index;
+// FP64 block partial of w.
 __global__ __launch_bounds__(kRedBlock) void k_combine(const float* __restrict__ part, int split,
-                                                       int64_t mpad, int64_t m, bool grad,
-                                                       float ascale, bool kahan,
+                                                       int64_t mpad, int64_t m, bool grad, Scale sc,
+                                                       bool kahan, const int32_t* __restrict__ qperm,
                                                        float* __restrict__ wout,
                                                        float* __restrict__ gout,
                                                        double* __restrict__ blk) {
@@ -240,31 +351,16 @@ __global__ __launch_bounds__(kRedBlock) void k_combine(const float* __restrict__
   double wv = 0.0;
   if (i < m) {
     const int na = grad ? kNAcc : 1;
-    float w;
-    if (na == 1) {
-      // eval-only partials are laid out [split][1][mpad]
-      float s = 0.0f, c = 0.0f;
-      for (int p = 0; p < split; ++p) {
-        const float x = part[(int64_t)p * mpad + i];
-        if (kahan) {
-          const float y = x - c;
-          const float t = s + y;
-          c = (t - s) - y;
-          s = t;
-        } else {
-          s += x;
-        }
-      }
-      w = kahan ? s - c : s;
-    } else {
-      w = combine(part, split, mpad, 0, i, kahan);
+    const int64_t o = qperm[i];
+    const float w = sc.ws * combine(part, split, mpad, na, 0, i, kahan);
+    if (grad) {
       for (int d = 0; d < 3; ++d) {
-        const float A = combine(part, split, mpad, 1 + d, i, kahan);
-        const float B = combine(part, split, mpad, 4 + d, i, kahan);
-        gout[d * m + i] = fmaf(ascale, A, -B);
+        const float A = combine(part, split, mpad, na, 1 + d, i, kahan);
+        const float B = combine(part, split, mpad, na, 4 + d, i, kahan);
+        gout[d * m + o] = fmaf(sc.as, A, -sc.bs * B);
       }
     }
-    if (wout) wout[i] = w;
+    if (wout) wout[o] = w;
     wv = (double)w;
   }
   const double bs = block_sum(wv, lds);
@@ -272,11 +368,12 @@ __global__ __launch_bounds__(kRedBlock) void k_combine(const float* __restrict__
 }
 
 // Iteration epilogue (Eq. 7): n_new = -grad/|grad| (kept when |grad| is 0 or not finite),
-// written in place; restage m for the next iteration; theta_i (degrees, FP64); FP64 block
-// partials of w and of the chord |n_new - n_old|.
+// written in place at the point's original index; restage m for the next iteration;
+// theta_i (degrees, FP64); FP64 block partials of w and of the chord |n_new - n_old|.
 __global__ __launch_bounds__(kRedBlock) void k_update(const float* __restrict__ part, int split,
-                                                      int64_t mpad, int64_t n, float ascale,
-                                                      bool kahan, const float* __restrict__ kk,
+                                                      int64_t mpad, int64_t n, Scale sc, bool kahan,
+                                                      const int32_t* __restrict__ perm,
+                                                      const float* __restrict__ kk,
                                                       float* __restrict__ N,
                                                       float4* __restrict__ src,
                                                       double* __restrict__ theta,
@@ -285,14 +382,15 @@ __global__ __launch_bounds__(kRedBlock) void k_update(const float* __restrict__ 
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double wv = 0.0, cv = 0.0;
   if (i < n) {
-    const float w = combine(part, split, mpad, 0, i, kahan);
+    const float w = sc.ws * combine(part, split, mpad, kNAcc, 0, i, kahan);
     float g[3];
     for (int d = 0; d < 3; ++d) {
-      const float A = combine(part, split, mpad, 1 + d, i, kahan);
-      const float B = combine(part, split, mpad, 4 + d, i, kahan);
-      g[d] = fmaf(ascale, A, -B);
+      const float A = combine(part, split, mpad, kNAcc, 1 + d, i, kahan);
+      const float B = combine(part, split, mpad, kNAcc, 4 + d, i, kahan);
+      g[d] = fmaf(sc.as, A, -sc.bs * B);
     }
-    const float o0 = N[i], o1 = N[n + i], o2 = N[2 * n + i];
+    const int64_t o = perm[i];
+    const float o0 = N[o], o1 = N[n + o], o2 = N[2 * n + o];
     const double gl = sqrt((double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2]);
     float n0 = o0, n1 = o1, n2 = o2;
     if (gl > 0.0 && gl <= 1.7976931348623157e308) {
@@ -304,9 +402,9 @@ __global__ __launch_bounds__(kRedBlock) void k_update(const float* __restrict__ 
     const double ch = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
     const double h = 0.5 * ch;
     theta[i] = 2.0 * asin(h < 1.0 ? h : 1.0) * kRadToDeg;
-    N[i] = n0;
-    N[n + i] = n1;
-    N[2 * n + i] = n2;
+    N[o] = n0;
+    N[n + o] = n1;
+    N[2 * n + o] = n2;
     const float k = kk[i];
     src[2 * i + 1] = make_float4(k * n0, k * n1, k * n2, 0.0f);
     wv = (double)w;
@@ -438,11 +536,12 @@ __global__ void k_random_normals(uint64_t seed, int64_t n, float* __restrict__ N
 }
 
 template <int QPT, bool GRAD, bool SCREENED, bool KAHAN>
-void launch_gwn_t(dim3 grid, hipStream_t st, const float* Q, int64_t m, const GwnWork& w,
-                  int64_t tps, float s) {
-  const float neg_s_log2e = -s * 1.4426950408889634f;
-  hipLaunchKernelGGL((k_gwn<QPT, GRAD, SCREENED, KAHAN>), grid, dim3(kBlock), 0, st, Q, m, w.src,
-                     w.ntiles, tps, s, neg_s_log2e, s * s, w.part, w.mpad);
+void launch_gwn_t(dim3 grid, hipStream_t st, const float* Q, int64_t m, const int32_t* qperm,
+                  const GwnWork& w, int64_t tps, float s) {
+  const Scr sk{3.0f * s, -s * 1.4426950408889634f, s * s};
+  const int64_t nfull = w.n_src / kTile;  // tiles without padding
+  hipLaunchKernelGGL((k_gwn<QPT, GRAD, SCREENED, KAHAN>), grid, dim3(kBlock), 0, st, Q, m, qperm, w.src,
+                     w.ntiles, nfull, tps, w.tbox, w.qbox, sk, w.part, w.mpad);
 }
 
 }  // namespace
@@ -458,8 +557,9 @@ int choose_split(int64_t n_src, int64_t n_qry, int requested) {
   return (int)s;
 }
 
-size_t carve_gwn(Carver& c, int64_t n_src, int64_t n_qry, int split, GwnWork* out) {
+size_t carve_gwn(Carver& c, int64_t n_src, int64_t n_qry, int split, bool same, GwnWork* out) {
   GwnWork w{};
+  w.n_src = n_src;
   w.ntiles = cdiv(n_src, kTile);
   w.npad = w.ntiles * kTile;
   w.mpad = cdiv(n_qry, kQBlock) * kQBlock;
@@ -474,6 +574,11 @@ size_t carve_gwn(Carver& c, int64_t n_src, int64_t n_qry, int split, GwnWork* ou
   w.stats = c.take<double>(4);
   w.hist = c.take<uint32_t>(256);
   w.sel = c.take<uint64_t>(2);
+  w.tbox = c.take<float4>(2 * (size_t)w.ntiles);
+  w.qbox = c.take<float4>(2 * (size_t)(w.mpad / kQBlock));
+  w.perm_s = c.take<int32_t>((size_t)w.npad);
+  w.perm_q = same ? w.perm_s : c.take<int32_t>((size_t)w.mpad);
+  carve_sort(c, std::max(n_src, n_qry), &w.sort);
   if (out) *out = w;
   return c.used - start;
 }
@@ -481,7 +586,23 @@ size_t carve_gwn(Carver& c, int64_t n_src, int64_t n_qry, int split, GwnWork* ou
 dwg_status launch_stage(const float* P, const float* N, const float* area, const float* delta,
                         int64_t n, float eps, const GwnWork& w, hipStream_t stream) {
   hipLaunchKernelGGL(k_stage, dim3((unsigned)cdiv(w.npad, 256)), dim3(256), 0, stream, P, N, area,
-                     delta, n, w.npad, eps, w.src, w.kk);
+                     delta, n, w.npad, eps, w.perm_s, w.src, w.kk);
+  DWG_TRY_LAUNCH();
+  hipLaunchKernelGGL(k_tile_box, dim3((unsigned)w.ntiles), dim3(kTile), 0, stream, w.src, n, w.tbox);
+  DWG_TRY_LAUNCH();
+  return DWG_OK;
+}
+
+dwg_status launch_order(const float* P, int64_t n, const float* delta, float eps, const float* Q, int64_t m,
+                        bool same, const GwnWork& w, hipStream_t stream) {
+  dwg_status s = spatial_sort(P, n, delta, eps, w.sort, w.perm_s, stream);
+  if (s != DWG_OK) return s;
+  if (!same) {
+    s = spatial_sort(Q, m, nullptr, 0.0f, w.sort, w.perm_q, stream);
+    if (s != DWG_OK) return s;
+  }
+  hipLaunchKernelGGL(k_query_box, dim3((unsigned)(w.mpad / kQBlock)), dim3(kBlock), 0, stream, Q, m, w.perm_q,
+                     w.qbox);
   DWG_TRY_LAUNCH();
   return DWG_OK;
 }
@@ -495,7 +616,7 @@ dwg_status launch_gwn(const float* Q, int64_t m, const dwg_kernel_params& kp, bo
   const bool kah = kp.compensated != 0;
   const float s = sqrtf(kp.lambda);
 #define DWG_GWN_CASE(G, S, K) \
-  if (grad == G && scr == S && kah == K) launch_gwn_t<kQpt, G, S, K>(grid, stream, Q, m, w, tps, s);
+  if (grad == G && scr == S && kah == K) launch_gwn_t<kQpt, G, S, K>(grid, stream, Q, m, w.perm_q, w, tps, s);
   DWG_GWN_CASE(true, false, true)
   DWG_GWN_CASE(true, false, false)
   DWG_GWN_CASE(true, true, true)
@@ -512,9 +633,8 @@ dwg_status launch_gwn(const float* Q, int64_t m, const dwg_kernel_params& kp, bo
 dwg_status launch_combine(int64_t m, const dwg_kernel_params& kp, bool grad, float* wout,
                           float* gout, double* wmean, const GwnWork& w, hipStream_t stream) {
   const int nb = (int)cdiv(m, kRedBlock);
-  const float ascale = kp.lambda > 0.0f ? 1.0f : 3.0f;
   hipLaunchKernelGGL(k_combine, dim3(nb), dim3(kRedBlock), 0, stream, w.part, w.split, w.mpad, m, grad,
-                     ascale, kp.compensated != 0, wout, gout, w.blk);
+                     scale_of(kp), kp.compensated != 0, w.perm_q, wout, gout, w.blk);
   DWG_TRY_LAUNCH();
   if (wmean) {
     hipLaunchKernelGGL(k_sums, dim3(1), dim3(kRedBlock), 0, stream, w.blk, nb, m, (int64_t)1, 0,
@@ -525,13 +645,11 @@ dwg_status launch_combine(int64_t m, const dwg_kernel_params& kp, bool grad, flo
   return DWG_OK;
 }
 
-dwg_status launch_update(int64_t n, const float* area, const dwg_kernel_params& kp, float* N,
-                         const GwnWork& w, hipStream_t stream) {
-  (void)area;
+dwg_status launch_update(int64_t n, const dwg_kernel_params& kp, float* N, const GwnWork& w,
+                         hipStream_t stream) {
   const int nb = (int)cdiv(n, kRedBlock);
-  const float ascale = kp.lambda > 0.0f ? 1.0f : 3.0f;
-  hipLaunchKernelGGL(k_update, dim3(nb), dim3(kRedBlock), 0, stream, w.part, w.split, w.mpad, n, ascale,
-                     kp.compensated != 0, w.kk, N, w.src, w.theta, w.blk, nb);
+  hipLaunchKernelGGL(k_update, dim3(nb), dim3(kRedBlock), 0, stream, w.part, w.split, w.mpad, n, scale_of(kp),
+                     kp.compensated != 0, w.perm_s, w.kk, N, w.src, w.theta, w.blk, nb);
   DWG_TRY_LAUNCH();
   return DWG_OK;
 }

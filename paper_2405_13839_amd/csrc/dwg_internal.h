@@ -54,36 +54,104 @@ struct Carver {
 // Split count for the all-pairs kernels.
 int choose_split(int64_t n_src, int64_t n_qry, int requested);
 
+// Uniform grid over a reference point set (dwg_knn.hip).
+struct GridParams {
+  float ox, oy, oz;  // origin (bbox min)
+  float h, ih;       // cell size and its inverse
+  int nx, ny, nz;
+  int64_t ncells;
+};
+struct KnnWork {
+  float* bbox_part;  // [256 * 6] per-block bbox partials
+  GridParams* gp;
+  int32_t* key;      // [nr] cell of each reference point
+  int32_t* start;    // [max_cells + 1] first sorted slot of each cell
+  int32_t* cursor;   // [max_cells] scatter cursors
+  int32_t* sums;     // scan tile totals
+  float4* sorted;    // [nr] (x, y, z, index bits) in cell order
+};
+size_t carve_knn(Carver& c, int64_t nr, KnnWork* out);
+
+// Anchor features of the learned initial normals: anchors, their grid, chunk buffers.
+constexpr int64_t DWG_FEAT_ANCHORS = 4096;
+struct AnchorCtx {
+  float* A;            // [3][na] anchor coordinates
+  int32_t* idx;        // [chunk][16]
+  float* dist;         // [chunk][16]
+  float* feat;         // [chunk][48]
+  int64_t na, stride, chunk;
+  KnnWork w;
+};
+size_t carve_anchor(Carver& c, int64_t n, int64_t chunk, int64_t n_anchor, AnchorCtx* out);
+size_t anchor_ws_bytes(int64_t n, int64_t chunk);
+dwg_status anchor_build(const float* P, int64_t n, const AnchorCtx& x, hipStream_t stream);
+dwg_status anchor_features(const float* P, int64_t n, int64_t q0, int64_t m, const AnchorCtx& x, float* feat,
+                           hipStream_t stream);
+
+// Bounding box of a planar [3][n] array: part [256 * 6] scratch, out6 = min xyz, max xyz.
+constexpr int kBboxParts = 256 * 6;
+dwg_status launch_bbox(const float* R, int64_t n, float* part, float* out6, hipStream_t st);
+// In-place exclusive scan of a[0..n), total written to a[n]; sums has scan_sums_len(n) slots.
+size_t scan_sums_len(int64_t n);
+dwg_status exclusive_scan(int32_t* a, int64_t n, int32_t* sums, hipStream_t st);
+
+// Spatial order of a point set for the all-pairs kernel (dwg_sort.hip).
+struct SortWork {
+  float* part;      // [kBboxParts]
+  float* box;       // [8]: bbox and the mean kernel radius
+  double* rpart;    // [256] radius partial sums
+  uint32_t* key;    // [n]
+  int32_t* bins;    // [kSortBins + 1]
+  int32_t* cursor;  // [kSortBins]
+  int32_t* sums;    // scan tile totals
+};
+constexpr int64_t kSortBins = int64_t(2) << 21;  // 2 radius classes x 2^21 Morton cells
+size_t carve_sort(Carver& c, int64_t n, SortWork* out);
+// perm[i] = original index of the i-th point in spatial order (deterministic).
+dwg_status spatial_sort(const float* P, int64_t n, const float* delta, float eps, const SortWork& w,
+                        int32_t* perm, hipStream_t st);
+
 // Device-side state of one GWN / iteration launch sequence, carved from the workspace.
+// Sources and queries are processed in spatial order (perm_s / perm_q: sorted position ->
+// original index); outputs are written back at the original indices.
 struct GwnWork {
-  float4* src;        // [2 * npad]: (px,py,pz,1/rho_min), (mx,my,mz,0) per source
-  float* part;        // [split][kNAcc][mpad] per-split partial sums
+  float4* src;        // [2 * npad]: (px,py,pz,1/rho_min), (mx,my,mz,0) per sorted source
+  float* part;        // [split][kNAcc][mpad] per-split partial sums (sorted queries)
   float* kk;          // [npad] a_j / (4 pi), for restaging after the update
   double* theta;      // [m] angle change in degrees (iterate)
   double* blk;        // [2 * nblk] per-block FP64 partial sums
   double* stats;      // [4] device statistics
   uint32_t* hist;     // [256] radix histogram
   uint64_t* sel;      // [2]: radix prefix, remaining count
-  int64_t npad, mpad, ntiles;
+  float4* tbox;       // [2 * ntiles] source tile boxes and radii
+  float4* qbox;       // [2 * mpad / kQBlock] query block boxes
+  int32_t* perm_s;    // [npad]
+  int32_t* perm_q;    // [mpad] (== perm_s when the queries are the sources)
+  SortWork sort;
+  int64_t n_src, npad, mpad, ntiles;
   int split;
   int nblk;           // blocks of the O(n) epilogue kernels
 };
 
-size_t carve_gwn(Carver& c, int64_t n_src, int64_t n_qry, int split, GwnWork* out);
+size_t carve_gwn(Carver& c, int64_t n_src, int64_t n_qry, int split, bool same, GwnWork* out);
 
 // Workspace bytes of the kNN / features / MLP stages for n points.
 size_t knn_ws_bytes(int64_t n_ref, int64_t n_qry);
 size_t mlp_ws_bytes(int64_t B);
+dwg_status mlp_forward(const float* params, const float* X, int64_t B, float* Y, int64_t sr, int64_t sc,
+                       hipStream_t stream);
 
 // Launchers (all enqueue on `stream`; return DWG_OK or DWG_E_DEVICE).
+dwg_status launch_order(const float* P, int64_t n, const float* delta, float eps, const float* Q, int64_t m,
+                        bool same, const GwnWork& w, hipStream_t stream);
 dwg_status launch_stage(const float* P, const float* N, const float* area, const float* delta,
                         int64_t n, float eps, const GwnWork& w, hipStream_t stream);
 dwg_status launch_gwn(const float* Q, int64_t m, const dwg_kernel_params& kp, bool grad,
                       const GwnWork& w, hipStream_t stream);
 dwg_status launch_combine(int64_t m, const dwg_kernel_params& kp, bool grad, float* wout,
                           float* gout, double* wmean, const GwnWork& w, hipStream_t stream);
-dwg_status launch_update(int64_t n, const float* area, const dwg_kernel_params& kp, float* N,
-                         const GwnWork& w, hipStream_t stream);
+dwg_status launch_update(int64_t n, const dwg_kernel_params& kp, float* N, const GwnWork& w,
+                         hipStream_t stream);
 dwg_status launch_stats(int64_t n, double top_frac, const GwnWork& w, hipStream_t stream);
 dwg_status launch_random_normals(uint64_t seed, int64_t n, float* N, hipStream_t stream);
 

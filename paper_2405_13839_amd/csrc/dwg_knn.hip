@@ -20,12 +20,6 @@ constexpr int kScanBlock = 256;
 constexpr int kScanItems = 4;  // elements per thread in the block scan
 constexpr int kScanTile = kScanBlock * kScanItems;
 
-struct GridParams {
-  float ox, oy, oz;  // origin (bbox min)
-  float h, ih;       // cell size and its inverse
-  int nx, ny, nz;
-  int64_t ncells;
-};
 
 __global__ __launch_bounds__(256) void k_bbox_partial(const float* __restrict__ R, int64_t n,
                                                       float* __restrict__ part) {
@@ -53,6 +47,21 @@ __global__ __launch_bounds__(256) void k_bbox_partial(const float* __restrict__ 
     __syncthreads();
   }
   if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = lds[threadIdx.x][0];
+}
+
+// Final bounding box: out6 = (min x, min y, min z, max x, max y, max z).
+__global__ void k_bbox_final(const float* __restrict__ part, int nblocks, float* __restrict__ out6) {
+  if (threadIdx.x != 0) return;
+  float mn[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, mx[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
+  for (int b = 0; b < nblocks; ++b)
+    for (int d = 0; d < 3; ++d) {
+      mn[d] = fminf(mn[d], part[b * 6 + d]);
+      mx[d] = fmaxf(mx[d], part[b * 6 + 3 + d]);
+    }
+  for (int d = 0; d < 3; ++d) {
+    out6[d] = mn[d];
+    out6[3 + d] = mx[d];
+  }
 }
 
 // Final bbox and grid parameters (single thread; nblocks is small).
@@ -205,9 +214,11 @@ __device__ __forceinline__ bool less_pair(float d2, int i, float e2, int j) {
 }
 
 // skip_mode: 0 none; 1 reference i == query i; 2 reference i / stride when i % stride == 0.
+// Queries q = 0..m-1 are points q0 + q of the planar array Q with leading dimension qld;
+// results go to idx[q][K], dist[q][K].
 template <int K>
-__global__ __launch_bounds__(256) void k_knn(const float* __restrict__ Q, int64_t m,
-                                             const GridParams* __restrict__ gp,
+__global__ __launch_bounds__(256) void k_knn(const float* __restrict__ Q, int64_t qld, int64_t q0,
+                                             int64_t m, const GridParams* __restrict__ gp,
                                              const int32_t* __restrict__ start,
                                              const float4* __restrict__ sorted, int skip_mode,
                                              int64_t stride, int32_t* __restrict__ idx,
@@ -215,10 +226,11 @@ __global__ __launch_bounds__(256) void k_knn(const float* __restrict__ Q, int64_
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= m) return;
   const GridParams g = *gp;
-  const float qx = Q[q], qy = Q[m + q], qz = Q[2 * m + q];
+  const int64_t gq = q0 + q;
+  const float qx = Q[gq], qy = Q[qld + gq], qz = Q[2 * qld + gq];
   int skip = -1;
-  if (skip_mode == 1) skip = (int)q;
-  if (skip_mode == 2 && (q % stride) == 0) skip = (int)(q / stride);
+  if (skip_mode == 1) skip = (int)gq;
+  if (skip_mode == 2 && (gq % stride) == 0) skip = (int)(gq / stride);
   float bd[K];
   int bi[K];
 #pragma unroll
@@ -298,17 +310,19 @@ __global__ void k_gather_anchors(const float* __restrict__ P, int64_t n, int64_t
   A[2 * na + a] = P[2 * n + i];
 }
 
-// feat[i][3k + d] = (anchor_k - p_i)_d / s_i, s_i = mean of the 16 anchor distances.
-__global__ void k_features(const float* __restrict__ P, int64_t n, const float* __restrict__ A,
-                           int64_t na, const int32_t* __restrict__ idx,
+// feat[i][3k + d] = (anchor_k - p_i)_d / s_i, s_i = mean of the 16 anchor distances, for
+// the points q0 + i, i = 0..m-1 (idx, dist, feat are chunk-local).
+__global__ void k_features(const float* __restrict__ P, int64_t n, int64_t q0, int64_t m,
+                           const float* __restrict__ A, int64_t na, const int32_t* __restrict__ idx,
                            const float* __restrict__ dist, float* __restrict__ feat) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= m) return;
   float s = 0.0f;
   for (int t = 0; t < DWG_FEAT_K; ++t) s += dist[i * DWG_FEAT_K + t];
   s *= (1.0f / DWG_FEAT_K);
   const float is = s > 0.0f ? 1.0f / s : 0.0f;
-  const float px = P[i], py = P[n + i], pz = P[2 * n + i];
+  const int64_t gi = q0 + i;
+  const float px = P[gi], py = P[n + gi], pz = P[2 * n + gi];
   for (int t = 0; t < DWG_FEAT_K; ++t) {
     const int64_t a = idx[i * DWG_FEAT_K + t];
     feat[i * DWG_MLP_IN + 3 * t + 0] = (A[a] - px) * is;
@@ -317,43 +331,18 @@ __global__ void k_features(const float* __restrict__ P, int64_t n, const float* 
   }
 }
 
-struct KnnWork {
-  float* bbox_part;  // [kBboxBlocks * 6]
-  GridParams* gp;
-  int32_t* key;      // [nr]
-  int32_t* start;    // [max_cells + 1]
-  int32_t* cursor;   // [max_cells]
-  int32_t* sums;     // [tiles]
-  float4* sorted;    // [nr]
-};
-
 constexpr int kBboxBlocks = 256;
 
 int64_t max_cells_for(int64_t nr) { return std::max<int64_t>(8 * nr, 64); }
-
-size_t carve_knn(Carver& c, int64_t nr, KnnWork* out) {
-  const int64_t mc = max_cells_for(nr);
-  const size_t s0 = c.used;
-  KnnWork w;
-  w.bbox_part = c.take<float>(kBboxBlocks * 6);
-  w.gp = c.take<GridParams>(1);
-  w.key = c.take<int32_t>((size_t)nr);
-  w.start = c.take<int32_t>((size_t)mc + 1);
-  w.cursor = c.take<int32_t>((size_t)mc);
-  w.sums = c.take<int32_t>((size_t)cdiv(mc, kScanTile) + 1);
-  w.sorted = c.take<float4>((size_t)nr);
-  if (out) *out = w;
-  return c.used - s0;
-}
 
 unsigned grid_for(int64_t n, int block = 256, int64_t cap = 65535) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, block), cap));
 }
 
 template <int K>
-void launch_knn_k(int64_t m, hipStream_t st, const float* Q, const KnnWork& w, int skip_mode,
-                  int64_t stride, int32_t* idx, float* dist) {
-  hipLaunchKernelGGL(k_knn<K>, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, st, Q, m, w.gp, w.start,
+void launch_knn_k(int64_t m, hipStream_t st, const float* Q, int64_t qld, int64_t q0, const KnnWork& w,
+                  int skip_mode, int64_t stride, int32_t* idx, float* dist) {
+  hipLaunchKernelGGL(k_knn<K>, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, st, Q, qld, q0, m, w.gp, w.start,
                      w.sorted, skip_mode, stride, idx, dist);
 }
 
@@ -382,11 +371,11 @@ dwg_status build_grid(const float* R, int64_t nr, const KnnWork& w, hipStream_t 
   return DWG_OK;
 }
 
-dwg_status knn_query(const float* Q, int64_t m, const KnnWork& w, int skip_mode, int64_t stride, int k,
-                     int32_t* idx, float* dist, hipStream_t st) {
+dwg_status knn_query(const float* Q, int64_t qld, int64_t q0, int64_t m, const KnnWork& w, int skip_mode,
+                     int64_t stride, int k, int32_t* idx, float* dist, hipStream_t st) {
   switch (k) {
 #define DWG_K(KK) \
-  case KK: launch_knn_k<KK>(m, st, Q, w, skip_mode, stride, idx, dist); break;
+  case KK: launch_knn_k<KK>(m, st, Q, qld, q0, w, skip_mode, stride, idx, dist); break;
     DWG_K(1) DWG_K(2) DWG_K(3) DWG_K(4) DWG_K(5) DWG_K(6) DWG_K(7) DWG_K(8)
     DWG_K(9) DWG_K(10) DWG_K(11) DWG_K(12) DWG_K(13) DWG_K(14) DWG_K(15) DWG_K(16)
 #undef DWG_K
@@ -397,6 +386,42 @@ dwg_status knn_query(const float* Q, int64_t m, const KnnWork& w, int skip_mode,
 }
 
 }  // namespace
+
+size_t carve_knn(Carver& c, int64_t nr, KnnWork* out) {
+  const int64_t mc = max_cells_for(nr);
+  const size_t s0 = c.used;
+  KnnWork w;
+  w.bbox_part = c.take<float>(kBboxBlocks * 6);
+  w.gp = c.take<GridParams>(1);
+  w.key = c.take<int32_t>((size_t)nr);
+  w.start = c.take<int32_t>((size_t)mc + 1);
+  w.cursor = c.take<int32_t>((size_t)mc);
+  w.sums = c.take<int32_t>((size_t)cdiv(mc, kScanTile) + 1);
+  w.sorted = c.take<float4>((size_t)nr);
+  if (out) *out = w;
+  return c.used - s0;
+}
+
+dwg_status launch_bbox(const float* R, int64_t n, float* part, float* out6, hipStream_t st) {
+  hipLaunchKernelGGL(k_bbox_partial, dim3(kBboxBlocks), dim3(256), 0, st, R, n, part);
+  DWG_TRY_LAUNCH();
+  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, part, kBboxBlocks, out6);
+  DWG_TRY_LAUNCH();
+  return DWG_OK;
+}
+
+size_t scan_sums_len(int64_t n) { return (size_t)cdiv(n, kScanTile) + 1; }
+
+dwg_status exclusive_scan(int32_t* a, int64_t n, int32_t* sums, hipStream_t st) {
+  const int64_t nt = cdiv(n, kScanTile);
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(kScanBlock), 0, st, a, n, sums);
+  DWG_TRY_LAUNCH();
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, sums, nt, a, n);
+  DWG_TRY_LAUNCH();
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, a, n, sums);
+  DWG_TRY_LAUNCH();
+  return DWG_OK;
+}
 
 size_t knn_ws_bytes(int64_t n_ref, int64_t n_qry) {
   (void)n_qry;
@@ -415,7 +440,7 @@ dwg_status knn_run(const float* R, int64_t nr, const float* Q, int64_t m, int se
   carve_knn(c, nr, &w);
   dwg_status s = build_grid(R, nr, w, stream);
   if (s != DWG_OK) return s;
-  return knn_query(Q, m, w, self_skip ? 1 : 0, 1, k, idx, dist, stream);
+  return knn_query(Q, m, 0, m, w, self_skip ? 1 : 0, 1, k, idx, dist, stream);
 }
 
 dwg_status delta_from_knn(const float* dist, int64_t n, int k, float scale, float* delta,
@@ -425,29 +450,56 @@ dwg_status delta_from_knn(const float* dist, int64_t n, int k, float scale, floa
   return DWG_OK;
 }
 
-// Anchors: every stride-th point, stride = max(1, n / n_anchor).
+size_t anchor_ws_bytes(int64_t n, int64_t chunk) {
+  Carver c(nullptr);
+  AnchorCtx x;
+  carve_anchor(c, n, chunk, DWG_FEAT_ANCHORS, &x);
+  return c.used;
+}
+
+size_t carve_anchor(Carver& c, int64_t n, int64_t chunk, int64_t n_anchor, AnchorCtx* out) {
+  const size_t s0 = c.used;
+  AnchorCtx x;
+  x.stride = std::max<int64_t>(1, n / std::max<int64_t>(n_anchor, 1));
+  x.na = cdiv(n, x.stride);
+  x.chunk = chunk;
+  x.A = c.take<float>(3 * (size_t)x.na);
+  x.idx = c.take<int32_t>((size_t)chunk * DWG_FEAT_K);
+  x.dist = c.take<float>((size_t)chunk * DWG_FEAT_K);
+  x.feat = c.take<float>((size_t)chunk * DWG_MLP_IN);
+  carve_knn(c, x.na, &x.w);
+  if (out) *out = x;
+  return c.used - s0;
+}
+
+// Anchors: every stride-th point, stride = max(1, n / n_anchor); grid over the anchors.
+dwg_status anchor_build(const float* P, int64_t n, const AnchorCtx& x, hipStream_t stream) {
+  hipLaunchKernelGGL(k_gather_anchors, dim3((unsigned)cdiv(x.na, 256)), dim3(256), 0, stream, P, n, x.stride,
+                     x.na, x.A);
+  DWG_TRY_LAUNCH();
+  return build_grid(x.A, x.na, x.w, stream);
+}
+
+// Features of the points q0 .. q0 + m - 1 (m <= chunk) into feat [m][48].
+dwg_status anchor_features(const float* P, int64_t n, int64_t q0, int64_t m, const AnchorCtx& x, float* feat,
+                           hipStream_t stream) {
+  dwg_status s = knn_query(P, n, q0, m, x.w, 2, x.stride, DWG_FEAT_K, x.idx, x.dist, stream);
+  if (s != DWG_OK) return s;
+  hipLaunchKernelGGL(k_features, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, stream, P, n, q0, m, x.A, x.na,
+                     x.idx, x.dist, feat);
+  DWG_TRY_LAUNCH();
+  return DWG_OK;
+}
+
 dwg_status features_run(const float* P, int64_t n, int64_t n_anchor, float* feat, void* ws,
                         size_t ws_bytes, hipStream_t stream) {
   (void)ws_bytes;
-  const int64_t stride = std::max<int64_t>(1, n / n_anchor);
-  const int64_t na = cdiv(n, stride);
   Carver c(ws);
-  float* A = c.take<float>(3 * (size_t)na);
-  int32_t* idx = c.take<int32_t>((size_t)n * DWG_FEAT_K);
-  float* dist = c.take<float>((size_t)n * DWG_FEAT_K);
-  KnnWork w;
-  carve_knn(c, na, &w);
-  hipLaunchKernelGGL(k_gather_anchors, dim3((unsigned)cdiv(na, 256)), dim3(256), 0, stream, P, n, stride,
-                     na, A);
-  DWG_TRY_LAUNCH();
-  dwg_status s = build_grid(A, na, w, stream);
+  AnchorCtx x;
+  carve_anchor(c, n, n, n_anchor, &x);
+  dwg_status s = anchor_build(P, n, x, stream);
   if (s != DWG_OK) return s;
-  s = knn_query(P, n, w, 2, stride, DWG_FEAT_K, idx, dist, stream);
-  if (s != DWG_OK) return s;
-  hipLaunchKernelGGL(k_features, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, stream, P, n, A, na, idx,
-                     dist, feat);
-  DWG_TRY_LAUNCH();
-  return DWG_OK;
+  return anchor_features(P, n, 0, n, x, feat, stream);
 }
 
 }  // namespace dwg

@@ -1,0 +1,98 @@
+"""GPU parity of the learned-init kernels (anchor features, BF16-MFMA MLP forward, backward
+and Adam) against the FP64 oracle on the same BF16-rounded operands."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp as om
+from paper_2405_13839_amd import mlp_init, synth
+from tests.helpers import cuda, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _dwg():
+    from paper_2405_13839_amd import dwg
+    return dwg
+
+
+def _rel_fro(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+@pytest.mark.parametrize("n,n_anchor", [(20_000, 4096), (6000, 512), (100, 17)])
+def test_features_match_oracle(n, n_anchor):
+    dwg = _dwg()
+    c = synth.torus_ellipsoids(max(n, 64), seed=40)
+    P = c.P[:, :n].copy()
+    f = host(dwg.features(cuda(P), n_anchor))
+    ref, amb = om.features(P, n_anchor)
+    ok = ~amb
+    assert ok.mean() >= 0.98
+    assert np.max(np.abs(f[ok] - ref[ok])) < 2e-4
+
+
+def _weights(seed):
+    blob = mlp_init.init_params(seed)
+    rng = np.random.default_rng(seed + 1)
+    blob[om.N_PARAMS - 3 - 3 * 128 - 128:] += rng.standard_normal(3 + 3 * 128 + 128).astype(np.float32) * 0.05
+    return blob
+
+
+@pytest.mark.parametrize("B", [1, 63, 64, 1000])
+def test_mlp_forward_matches_oracle(B):
+    dwg = _dwg()
+    blob = _weights(3)
+    rng = np.random.default_rng(B)
+    X = rng.standard_normal((B, 48)).astype(np.float32)
+    Y = host(dwg.mlp_infer(cuda(blob), cuda(X)))
+    _, yhat, _ = om.forward(blob, X)
+    assert _rel_fro(Y, yhat) < 1e-2
+    ang = np.degrees(np.arccos(np.clip(np.sum(Y * yhat, axis=1), -1, 1)))
+    assert np.mean(ang < 1.0) > 0.99
+
+
+def test_mlp_train_step_matches_oracle():
+    dwg = _dwg()
+    blob = _weights(5)
+    rng = np.random.default_rng(9)
+    B = 1000
+    X = rng.standard_normal((B, 48)).astype(np.float32)
+    T = rng.standard_normal((B, 3))
+    T = (T / np.linalg.norm(T, axis=1, keepdims=True)).astype(np.float32)
+    mask = (rng.uniform(size=B) < 0.9).astype(np.uint8)
+    p = cuda(blob)
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    lr = 1e-3
+    loss, g = dwg.mlp_train_step(p, m, v, 1, lr, cuda(X), cuda(T), cuda(mask, torch.uint8), want_grad=True)
+    rl, rg = om.loss_and_grad(blob, X, T, mask)
+    assert abs(host(loss)[0] - rl) <= 1e-4 * max(1.0, abs(rl))
+    g = host(g)
+    off = 0
+    for name, shp in om.SHAPES:
+        k = int(np.prod(shp))
+        assert _rel_fro(g[off:off + k], rg[off:off + k]) < 2e-2, name
+        off += k
+    # Adam at step 1 moves every parameter by -lr * g / (|g| + eps) (bias-corrected moments)
+    step = host(p) - blob
+    expect = -lr * g / (np.abs(g) + 1e-8)
+    np.testing.assert_allclose(step, expect, rtol=1e-3, atol=1e-9)
+
+
+def test_training_reduces_loss():
+    dwg = _dwg()
+    c = synth.torus_ellipsoids(20_000, seed=41)
+    X = dwg.features(cuda(c.P), 4096)
+    T = cuda(np.ascontiguousarray(c.N_true.T))
+    mask = cuda(c.inlier.astype(np.uint8), torch.uint8)
+    p = cuda(mlp_init.init_params(0))
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    losses = []
+    for step in range(1, 201):
+        loss, _ = dwg.mlp_train_step(p, m, v, step, 3e-3, X, T, mask)
+        losses.append(host(loss)[0])
+    assert np.mean(losses[-20:]) < 0.7 * np.mean(losses[:5])
