@@ -248,28 +248,32 @@ def _union_cloud(parts, n, noise_frac, outlier_frac, rng, oversample=1.25, meta=
     n_out = int(round(n * outlier_frac))
     n_in = n - n_out
     tot_area = sum(p.area for p in parts)
-    xs, ns, pid = [], [], []
-    vis_area = 0.0
-    overlap = np.eye(len(parts), dtype=bool)
-    for k, p in enumerate(parts):
-        m = int(math.ceil(oversample * n_in * p.area / tot_area)) + 8
-        x, nv = p.sample(rng, m)
-        keep = np.ones(m, dtype=bool)
-        for j, q in enumerate(parts):
-            if j != k:
-                ins = q.inside(x)
-                if ins.any():
-                    overlap[k, j] = overlap[j, k] = True
-                keep &= ~ins
-        vis_area += p.area * keep.mean()
-        xs.append(x[keep])
-        ns.append(nv[keep])
-        pid.append(np.full(int(keep.sum()), k))
-    x = np.concatenate(xs)
-    nv = np.concatenate(ns)
-    pid = np.concatenate(pid)
-    if x.shape[0] < n_in:
-        raise RuntimeError("oversampling too small for the union")
+    # draw uniform-by-area samples of every part; when heavy overlap leaves fewer than n_in
+    # visible samples, draw again with a larger oversampling factor
+    while True:
+        xs, ns, pid = [], [], []
+        vis_area = 0.0
+        overlap = np.eye(len(parts), dtype=bool)
+        for k, p in enumerate(parts):
+            m = int(math.ceil(oversample * n_in * p.area / tot_area)) + 8
+            x, nv = p.sample(rng, m)
+            keep = np.ones(m, dtype=bool)
+            for j, q in enumerate(parts):
+                if j != k:
+                    ins = q.inside(x)
+                    if ins.any():
+                        overlap[k, j] = overlap[j, k] = True
+                    keep &= ~ins
+            vis_area += p.area * keep.mean()
+            xs.append(x[keep])
+            ns.append(nv[keep])
+            pid.append(np.full(int(keep.sum()), k))
+        x = np.concatenate(xs)
+        nv = np.concatenate(ns)
+        pid = np.concatenate(pid)
+        if x.shape[0] >= n_in:
+            break
+        oversample *= 1.25 * n_in / max(x.shape[0], 1)
     sel = rng.choice(x.shape[0], size=n_in, replace=False)
     x, nv, pid = x[sel], nv[sel], pid[sel]
     # connected components of the overlap graph
