@@ -56,7 +56,7 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--lam", type=float, default=10.0)
     ap.add_argument("--init", choices=["auto", "mlp", "random"], default="auto")
-    ap.add_argument("--max-iters", type=int, default=30)
+    ap.add_argument("--max-iters", type=int, default=50)
     ap.add_argument("--compare-iters", type=int, default=20,
                     help="iteration cap of the one untimed random-init comparison solve (0 = skip)")
     ap.add_argument("--cpu-queries", type=int, default=4096,
