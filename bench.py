@@ -168,10 +168,12 @@ def main() -> int:
 
     if args.cpu_queries > 0:
         import oracle
+        # the oracle times the same kernel on synthetic inputs of the workload's shape
         rng = np.random.default_rng(7)
         sel = np.sort(rng.choice(n, min(args.cpu_queries, n), replace=False))
-        Nh = runs[-1][0].cpu().numpy()
-        dh = dwg.delta_knn_mean(P, 10, 2.0, ws=ws).cpu().numpy()
+        Nh = rng.standard_normal((3, n))
+        Nh /= np.linalg.norm(Nh, axis=0)
+        dh = np.full(n, 0.02)
         oracle.num_threads()
         t2 = time.perf_counter()
         oracle.gwn(cloud.P, Nh, cloud.area, dh, cloud.P[:, sel], lam=args.lam)

@@ -43,3 +43,12 @@ def angle_deg(a, b):
     b = np.asarray(b, np.float64)
     cr = np.linalg.norm(np.cross(a.T, b.T), axis=1)
     return np.degrees(np.arctan2(cr, np.sum(a * b, axis=0)))
+
+
+def knn_radius(P, k=10, scale=2.0):
+    """scale x mean distance to the k nearest other points, by scipy's cKDTree in float64
+    (an input for both sides that does not come from the GPU path)."""
+    from scipy.spatial import cKDTree
+    X = np.asarray(P, np.float64).T
+    d, _ = cKDTree(X).query(X, k=k + 1)
+    return (scale * d[:, 1:].mean(axis=1)).astype(np.float32)

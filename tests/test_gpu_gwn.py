@@ -10,7 +10,7 @@ import torch
 
 import oracle
 from paper_2405_13839_amd import synth
-from tests.helpers import TOL_G, TOL_W, cuda, e_g, e_w, host, unit_rows
+from tests.helpers import TOL_G, TOL_W, cuda, e_g, e_w, host, knn_radius, unit_rows
 
 pytestmark = pytest.mark.gpu
 
@@ -131,3 +131,20 @@ def test_nan_input_propagates():
     a[17] = np.nan
     w, g = dwg.gwn(cuda(P), cuda(N), cuda(a), cuda(d), cuda(P))
     assert torch.isnan(w).all()
+
+
+def test_gwn_grad_full_size_sampled():
+    """The bench configuration: 1M points (torus + 2 ellipsoids), screened lambda = 10, radius
+    2 x mean 10-NN, the split and spatial order the library picks; 200 sampled queries are
+    recomputed by the oracle one by one."""
+    dwg = _dwg()
+    c = synth.torus_ellipsoids(1_000_000, seed=102)
+    rng = np.random.default_rng(11)
+    N = unit_rows(rng, c.n)
+    Pc = cuda(c.P)
+    d = knn_radius(c.P)
+    w, g = dwg.gwn(Pc, cuda(N), cuda(c.area), cuda(d), Pc, dwg.Params(lam=10.0))
+    sel = rng.choice(c.n, 200, replace=False)
+    w_ref, g_ref, flag = oracle.gwn(c.P, N, c.area, d, c.P[:, sel], lam=10.0)
+    assert e_w(host(w)[sel], w_ref) <= TOL_W
+    assert e_g(host(g)[:, sel], g_ref, skip=flag) <= TOL_G

@@ -6,7 +6,7 @@ import torch
 
 import oracle
 from paper_2405_13839_amd import synth
-from tests.helpers import angle_deg, cuda, host
+from tests.helpers import angle_deg, cuda, host, knn_radius
 
 pytestmark = pytest.mark.gpu
 
@@ -131,3 +131,22 @@ def test_knn_and_delta_match_oracle(n, k):
         assert len(set(row.tolist())) == k
     delta = host(dwg.delta_knn_mean(Pc, k))
     np.testing.assert_allclose(delta[sel], rdist.mean(axis=1), rtol=3e-6)
+
+
+def test_one_iteration_sampled_at_100k():
+    """One screened iteration on 100K points (torus + ellipsoids): the GPU's new normals at 500
+    sampled points equal -grad w / |grad w| of the oracle's field of the initial normals."""
+    dwg = _dwg()
+    c = synth.torus_ellipsoids(100_000, seed=101)
+    rng = np.random.default_rng(3)
+    N0 = rng.standard_normal((3, c.n))
+    N0 = (N0 / np.linalg.norm(N0, axis=0)).astype(np.float32)
+    P = cuda(c.P)
+    d = knn_radius(c.P)
+    Ng = cuda(N0)
+    st, stats = dwg.iterate(P, cuda(c.area), cuda(d), Ng, dwg.Params(lam=10.0), max_iters=1, fixed_iters=True)
+    sel = rng.choice(c.n, 500, replace=False)
+    w_ref, g_ref, flag = oracle.gwn(c.P, N0, c.area, d, c.P[:, sel], lam=10.0)
+    n_ref = -g_ref / np.linalg.norm(g_ref, axis=0)
+    ang = angle_deg(host(Ng)[:, sel], n_ref)[~flag.astype(bool)]
+    assert ang.max() < 0.05
