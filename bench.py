@@ -4,8 +4,8 @@
 Workload (default): 1,000,000 points on a torus (R=1, r=0.3) united with 2 random
 ellipsoids (semi-axes U[0.2,0.6]), 5% uniform outliers, Gaussian noise 0.25% of the
 bounding-box diagonal, area weights = visible area / inliers, screened kernel lambda=10,
-kernel radius = 2 x mean 10-NN distance. Seeded synthetic data (the paper's scanned models
-are not available); see synth.torus_ellipsoids.
+kernel radius = mean distance to the 10 nearest of 4096 anchor points. Seeded synthetic data
+(the paper's scanned models are not available); see synth.torus_ellipsoids.
 
 One step = one complete orientation solve with the inputs resident in HBM: kNN radius,
 initial normals (learned MLP init when its weights exist, else random), then DWG
@@ -90,7 +90,7 @@ def main() -> int:
         mlp = mlp_init.load_params(WEIGHTS, dev)
 
     def solve(kind, max_iters, seed=202):
-        delta = dwg.delta_knn_mean(P, 10, 2.0, ws=ws)
+        delta = dwg.delta_anchor_mean(P, 10, 4096, 1.0, ws=ws)
         if kind == "mlp":
             N = dwg.mlp_normals(P, mlp, ws=ws)
         else:
@@ -133,7 +133,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {
             "workload": f"torus R=1 r=0.3 + 2 ellipsoids, {n} points (5% outliers, noise 0.25% diag), "
-                        f"screened lambda={args.lam}, radius 2x mean 10-NN, {init} init, solve to "
+                        f"screened lambda={args.lam}, anchor radius (10 of 4096), {init} init, solve to "
                         f"top-1% mean change <= 0.1 deg (cap {args.max_iters})",
             "n_points": n,
             "lambda": args.lam,

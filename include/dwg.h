@@ -157,6 +157,18 @@ dwg_status dwg_knn(const float* R, int64_t nr, const float* Q, int64_t m, int se
 dwg_status dwg_delta_knn_mean(const float* P, int64_t n, int k, float scale, float* delta,
                               void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * dwg_delta_anchor_mean -- resolution-independent kernel radius: delta_i = scale x mean
+ * distance from p_i to its k nearest "anchor" points (anchors = points whose index is a
+ * multiple of stride = max(1, n / n_anchor); an anchor never counts itself). A reading of
+ * the threshold of Sec. 5.2, whose absolute distance window assumes the paper's model
+ * normalisation: a fixed anchor count fixes the neighbourhood scale relative to the shape,
+ * as the paper's octree depth fixes the field's resolution. async. P [3][n]; delta: output
+ * [n]; 1 <= k <= 16; n_anchor > k; scale > 0.
+ */
+dwg_status dwg_delta_anchor_mean(const float* P, int64_t n, int k, int64_t n_anchor, float scale,
+                                 float* delta, void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------- learned initial normals
  * Features of point i: its 16 nearest "anchor" points (anchors = points whose index is a
  * multiple of `stride`, stride = max(1, n / n_anchor)), the anchor i itself excluded, as

@@ -194,3 +194,15 @@ def random_normals(seed: int, n: int):
     out = np.zeros((3, n))
     lib.orc_random_normals(ctypes.c_uint64(seed), n, _p(out))
     return out
+
+
+def anchor_delta(P, k=10, n_anchor=4096, scale=1.0):
+    """scale x mean distance from every point to its k nearest anchors (every stride-th
+    point, stride = max(1, n // n_anchor); an anchor skips itself)."""
+    P = _d(P)
+    n = P.shape[1]
+    stride = max(1, n // n_anchor)
+    A = np.ascontiguousarray(P[:, ::stride])
+    skip = np.where(np.arange(n) % stride == 0, np.arange(n) // stride, -1).astype(np.int32)
+    _, dist = knn(A, P, k, skip=skip)
+    return scale * dist.mean(axis=1)

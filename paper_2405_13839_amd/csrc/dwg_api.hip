@@ -320,6 +320,29 @@ dwg_status dwg_delta_knn_mean(const float* P, int64_t n, int k, float scale, flo
   return delta_from_knn(dist, n, k, scale, delta, st);
 }
 
+dwg_status dwg_delta_anchor_mean(const float* P, int64_t n, int k, int64_t n_anchor, float scale,
+                                 float* delta, void* ws, size_t ws_bytes, void* stream) {
+  DWG_CHECK(P && delta, "P and delta must not be NULL");
+  DWG_CHECK(k >= 1 && k <= kMaxK, "k must be in [1, %d]", kMaxK);
+  DWG_CHECK(n_anchor > k, "n_anchor must exceed k");
+  DWG_CHECK(n > k + 1 && n < (int64_t(1) << 31), "need k + 1 < n < 2^31");
+  DWG_CHECK(std::isfinite(scale) && scale > 0.0f, "scale must be finite and > 0");
+  const size_t need = aux_bytes(n);
+  DWG_CHECK(ws || ws_bytes == 0, "ws is NULL but ws_bytes > 0");
+  if (!ws || ws_bytes < need) {
+    set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+    return DWG_E_WORKSPACE;
+  }
+  DWG_PROPAGATE(check_device());
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Carver c(ws);
+  AnchorCtx x;
+  carve_anchor(c, n, feat_chunk(n), n_anchor, &x);
+  DWG_CHECK(x.na > k, "too few anchors (%lld) for k = %d", (long long)x.na, k);
+  DWG_PROPAGATE(anchor_build(P, n, x, st));
+  return anchor_delta(P, n, x, k, scale, delta, st);
+}
+
 int64_t dwg_mlp_param_count(void) {
   return (int64_t)DWG_MLP_HID * DWG_MLP_IN + DWG_MLP_HID + (int64_t)DWG_MLP_HID * DWG_MLP_HID +
          DWG_MLP_HID + (int64_t)DWG_MLP_OUT * DWG_MLP_HID + DWG_MLP_OUT;

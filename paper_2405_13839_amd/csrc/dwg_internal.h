@@ -28,7 +28,7 @@ void set_error(const char* fmt, ...);
 // ----------------------------------------------------------------------------- sizes
 constexpr int kBlock = 256;    // threads per block for the all-pairs kernels (4 waves)
 constexpr int kTile = 256;     // sources per LDS tile
-constexpr int kQpt = 4;        // queries held in registers per thread
+constexpr int kQpt = 2;        // queries held in registers per thread
 constexpr int kQBlock = kBlock * kQpt;  // queries per block
 constexpr int kNAcc = 7;       // per-query accumulators with the gradient: w, A[3], B[3]
 constexpr int kMaxSplit = 64;
@@ -87,6 +87,8 @@ size_t anchor_ws_bytes(int64_t n, int64_t chunk);
 dwg_status anchor_build(const float* P, int64_t n, const AnchorCtx& x, hipStream_t stream);
 dwg_status anchor_features(const float* P, int64_t n, int64_t q0, int64_t m, const AnchorCtx& x, float* feat,
                            hipStream_t stream);
+dwg_status anchor_delta(const float* P, int64_t n, const AnchorCtx& x, int k, float scale, float* delta,
+                        hipStream_t stream);
 
 // Bounding box of a planar [3][n] array: part [256 * 6] scratch, out6 = min xyz, max xyz.
 constexpr int kBboxParts = 256 * 6;

@@ -491,6 +491,20 @@ dwg_status anchor_features(const float* P, int64_t n, int64_t q0, int64_t m, con
   return DWG_OK;
 }
 
+// delta_i = scale x mean distance from p_i to its k nearest anchors (the anchor i itself
+// excluded), for all points in chunks of x.chunk.
+dwg_status anchor_delta(const float* P, int64_t n, const AnchorCtx& x, int k, float scale, float* delta,
+                        hipStream_t stream) {
+  for (int64_t q0 = 0; q0 < n; q0 += x.chunk) {
+    const int64_t cnt = std::min<int64_t>(x.chunk, n - q0);
+    dwg_status s = knn_query(P, n, q0, cnt, x.w, 2, x.stride, k, x.idx, x.dist, stream);
+    if (s != DWG_OK) return s;
+    s = delta_from_knn(x.dist, cnt, k, scale, delta + q0, stream);
+    if (s != DWG_OK) return s;
+  }
+  return DWG_OK;
+}
+
 dwg_status features_run(const float* P, int64_t n, int64_t n_anchor, float* feat, void* ws,
                         size_t ws_bytes, hipStream_t stream) {
   (void)ws_bytes;

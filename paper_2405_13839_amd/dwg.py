@@ -70,12 +70,14 @@ def load():
     lib.dwg_init_normals.argtypes = [i32, ctypes.c_uint64, vp, i64, vp, vp, vp, sz, vp]
     lib.dwg_knn.argtypes = [vp, i64, vp, i64, i32, i32, vp, vp, vp, sz, vp]
     lib.dwg_delta_knn_mean.argtypes = [vp, i64, i32, f32, vp, vp, sz, vp]
+    lib.dwg_delta_anchor_mean.argtypes = [vp, i64, i32, i64, f32, vp, vp, sz, vp]
     lib.dwg_mlp_param_count.restype = i64
     lib.dwg_features.argtypes = [vp, i64, i64, vp, vp, sz, vp]
     lib.dwg_mlp_infer.argtypes = [vp, vp, i64, vp, vp, sz, vp]
     lib.dwg_mlp_train_step.argtypes = [vp, vp, vp, i64, f32, vp, vp, vp, i64, vp, vp, vp, sz, vp]
     for name in ["dwg_gwn_eval", "dwg_gwn_grad", "dwg_iterate", "dwg_init_normals", "dwg_knn",
-                 "dwg_delta_knn_mean", "dwg_features", "dwg_mlp_infer", "dwg_mlp_train_step"]:
+                 "dwg_delta_knn_mean", "dwg_delta_anchor_mean", "dwg_features", "dwg_mlp_infer",
+                 "dwg_mlp_train_step"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -83,7 +85,8 @@ def load():
 
 EXPORTED = ["dwg_version", "dwg_status_string", "dwg_last_error", "dwg_workspace_bytes", "dwg_gwn_eval",
             "dwg_gwn_grad", "dwg_iterate", "dwg_init_normals", "dwg_knn", "dwg_delta_knn_mean",
-            "dwg_mlp_param_count", "dwg_features", "dwg_mlp_infer", "dwg_mlp_train_step"]
+            "dwg_delta_anchor_mean", "dwg_mlp_param_count", "dwg_features", "dwg_mlp_infer",
+            "dwg_mlp_train_step"]
 
 
 def version() -> str:
@@ -240,6 +243,19 @@ def delta_knn_mean(P, k: int = 10, scale: float = 1.0, ws=None) -> torch.Tensor:
     out = torch.empty(n, dtype=torch.float32, device=P.device)
     _check(lib.dwg_delta_knn_mean(_ptr(P), n, int(k), float(scale), _ptr(out), _ptr(ws), ws.numel(),
                                   _stream(P.device)))
+    return out
+
+
+def delta_anchor_mean(P, k: int = 10, n_anchor: int = 4096, scale: float = 1.0, ws=None) -> torch.Tensor:
+    """scale x mean distance to the k nearest of ~n_anchor anchor points, [n]."""
+    lib = load()
+    P = _dev(P, "P")
+    n = P.shape[1]
+    if ws is None:
+        ws = workspace(n, n, P.device)
+    out = torch.empty(n, dtype=torch.float32, device=P.device)
+    _check(lib.dwg_delta_anchor_mean(_ptr(P), n, int(k), int(n_anchor), float(scale), _ptr(out), _ptr(ws),
+                                     ws.numel(), _stream(P.device)))
     return out
 
 

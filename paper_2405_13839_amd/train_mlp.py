@@ -5,7 +5,8 @@
 
 Data: seeded shapes of the torus + 2 ellipsoids family (seeds 10000 + k, 5% outliers,
 noise 0.25% of the diagonal). Targets: the plain method's converged normals -- dwg_iterate
-(screened, lambda = 10, radius 2 x mean 10-NN distance) run to its convergence test from
+(screened, lambda = 10, radius = mean distance to the 10 nearest of 4096 anchors) run to its
+convergence test from
 the analytic normals, i.e. the fixed point of the same iteration in the consistently
 oriented basin -- with each component's sign fixed by the divergence theorem; outliers are
 masked out of the loss. Features: dwg_features (16 nearest of 4096 anchors). Optimiser:
@@ -45,7 +46,7 @@ def converged_targets(dwg, metrics, P, area, N_true, comp, lam, ws, dev, seed):
     n = P.shape[1]
     Pt = torch.from_numpy(P).to(dev)
     at = torch.from_numpy(area).to(dev)
-    d = dwg.delta_knn_mean(Pt, 10, 2.0, ws=ws)
+    d = dwg.delta_anchor_mean(Pt, 10, 4096, 1.0, ws=ws)
     N0 = dwg.random_normals(n, seed, dev)
     inl = torch.from_numpy(comp >= 0).to(dev)
     N0[:, inl] = torch.from_numpy(N_true).to(dev)[:, inl]
@@ -130,7 +131,7 @@ def main(argv=None) -> int:
     for k, (P, area, N_true, comp, inl) in enumerate(_shapes(range(20000, 20000 + args.eval), n, args.workers)):
         Pt = torch.from_numpy(P).to(dev)
         at = torch.from_numpy(area).to(dev)
-        d = dwg.delta_knn_mean(Pt, 10, 2.0, ws=ws)
+        d = dwg.delta_anchor_mean(Pt, 10, 4096, 1.0, ws=ws)
         row = {}
         for kind in ["mlp", "random"]:
             N0 = dwg.mlp_normals(Pt, blob, ws=ws) if kind == "mlp" else dwg.random_normals(n, 400000 + k, dev)

@@ -150,3 +150,16 @@ def test_one_iteration_sampled_at_100k():
     n_ref = -g_ref / np.linalg.norm(g_ref, axis=0)
     ang = angle_deg(host(Ng)[:, sel], n_ref)[~flag.astype(bool)]
     assert ang.max() < 0.05
+
+
+@pytest.mark.parametrize("n,n_anchor", [(3000, 300), (200_000, 4096)])
+def test_anchor_delta_matches_oracle(n, n_anchor):
+    dwg = _dwg()
+    c = synth.torus_ellipsoids(n, seed=32)
+    d = host(dwg.delta_anchor_mean(cuda(c.P), 10, n_anchor, 1.0))
+    sel = np.arange(n) if n <= 5000 else np.random.default_rng(1).choice(n, 4000, replace=False)
+    stride = max(1, n // n_anchor)
+    A = c.P[:, ::stride]
+    skip = np.where(sel % stride == 0, sel // stride, -1).astype(np.int32)
+    _, dist = oracle.knn(A, c.P[:, sel], 10, skip=skip)
+    np.testing.assert_allclose(d[sel], dist.mean(axis=1), rtol=3e-6)

@@ -38,7 +38,7 @@ def test_init_normals_mlp_matches_oracle():
 
 @pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights missing")
 def test_learned_init_gain_over_random():
-    """Held-out shapes (seeds 20000+) at 50K points, screened lambda = 10: from the learned
+    """Held-out shapes (seeds 20000+) at 50K points, screened lambda = 10, anchor radius: from the learned
     init the iteration passes its convergence test with <= 6 deg mean angle error and > 99%
     orientation agreement; from random normals it does not reach either within 100
     iterations on most shapes."""
@@ -48,7 +48,7 @@ def test_learned_init_gain_over_random():
     for seed in [20010, 20011, 20012, 20013]:
         c = synth.torus_ellipsoids(50_000, seed=seed)
         P, a = cuda(c.P), cuda(c.area)
-        d = dwg.delta_knn_mean(P, 10, 2.0)
+        d = dwg.delta_anchor_mean(P, 10, 4096, 1.0)
         row = {}
         for kind in ["mlp", "random"]:
             N = dwg.mlp_normals(P, mlp) if kind == "mlp" else dwg.random_normals(c.n, 7 + seed, "cuda")

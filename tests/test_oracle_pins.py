@@ -261,3 +261,17 @@ def test_sphere_method_level():
     cos = np.sum(NT * c.N_true, axis=0)
     agree = max(np.mean(cos > 0), np.mean(cos < 0))
     assert agree >= 0.999, agree
+
+
+def test_anchor_delta_against_kdtree():
+    """Radius from the k nearest anchors (every stride-th point, an anchor skips itself)."""
+    from scipy.spatial import cKDTree
+    c = synth.torus_ellipsoids(5000, seed=6)
+    P = c.P.astype(np.float64)
+    d = oracle.anchor_delta(P, k=10, n_anchor=300, scale=1.5)
+    stride = 5000 // 300
+    A = P[:, ::stride]
+    dd, ii = cKDTree(A.T).query(P.T, k=11)
+    is_anchor = np.arange(5000) % stride == 0
+    ref = np.where(is_anchor, dd[:, 1:].mean(axis=1), dd[:, :10].mean(axis=1)) * 1.5
+    np.testing.assert_allclose(d, ref, rtol=1e-12)
