@@ -156,10 +156,13 @@ class _Superquadric(_Part):
     def __init__(self, c, Rm, axes, e1, e2, rng):
         self.c, self.Rm, self.ax = np.asarray(c, float), np.asarray(Rm, float), np.asarray(axes, float)
         self.e1, self.e2 = float(e1), float(e2)
-        # area by quadrature of the parametric area element on a fine grid
-        eta, om, dA = self._grid(600, 1200)
-        self.area = float(np.sum(dA) * (math.pi / 600) * (2 * math.pi / 1200))
-        self.dAmax = float(dA.max()) * 1.05
+        # area by quadrature of the parametric area element on a fine grid; the cell areas
+        # also serve as the sampling table (cells drawn by area, uniform inside a cell)
+        self.ne, self.no = 600, 1200
+        eta, om, dA = self._grid(self.ne, self.no)
+        cell = dA.ravel() * (math.pi / self.ne) * (2 * math.pi / self.no)
+        self.area = float(np.sum(cell))
+        self.cdf = np.cumsum(cell) / np.sum(cell)
 
     def _pos(self, eta, om):
         a, b, c = self.ax
@@ -194,19 +197,12 @@ class _Superquadric(_Part):
         return np.linalg.norm(np.cross(xe, xo), axis=-1)
 
     def sample(self, rng, m):
-        xs, ns = [], []
-        got = 0
-        while got < m:
-            k = int((m - got) * 3) + 64
-            E = rng.uniform(-math.pi / 2, math.pi / 2, k)
-            O = rng.uniform(-math.pi, math.pi, k)
-            acc = rng.uniform(0, 1, k) * self.dAmax < self._dA(E, O)
-            x = self._pos(E[acc], O[acc])
-            xs.append(x)
-            ns.append(self._normal(x))
-            got += x.shape[0]
-        xl = np.concatenate(xs)[:m]
-        nl = np.concatenate(ns)[:m]
+        cells = np.minimum(np.searchsorted(self.cdf, rng.uniform(0, 1, m)), self.cdf.size - 1)
+        ie, io = np.divmod(cells, self.no)
+        E = -math.pi / 2 + (ie + rng.uniform(0, 1, m)) * math.pi / self.ne
+        O = -math.pi + (io + rng.uniform(0, 1, m)) * 2 * math.pi / self.no
+        xl = self._pos(E, O)
+        nl = self._normal(xl)
         return self.c + xl @ self.Rm.T, nl @ self.Rm.T
 
     def inside(self, x):
