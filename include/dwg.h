@@ -67,7 +67,12 @@ typedef struct dwg_iter_stat {
                           caller's stream), milliseconds */
 } dwg_iter_stat;
 
-typedef enum dwg_init_kind { DWG_INIT_RANDOM = 0, DWG_INIT_MLP = 1 } dwg_init_kind;
+typedef enum dwg_init_kind {
+  DWG_INIT_RANDOM = 0,  /* i.i.d. uniform unit normals (Algorithm 1) */
+  DWG_INIT_MLP = 1,     /* learned from anchor features (extension) */
+  DWG_INIT_PCA = 2,     /* smallest-eigenvalue eigenvector of the 16-NN covariance (Sec. 5.1) */
+  DWG_INIT_GAUSS = 3    /* Gauss map p / |p| about the origin (Sec. 5.1) */
+} dwg_init_kind;
 
 /* Library version string (static storage). */
 const char* dwg_version(void);
@@ -133,6 +138,13 @@ dwg_status dwg_iterate(const float* P, const float* area, const float* delta, in
  *     phi = 2 pi u1, n = (sqrt(1 - z^2) cos phi, sqrt(1 - z^2) sin phi, z). P may be NULL.
  *   DWG_INIT_MLP: the MLP of dwg_mlp_infer applied to the features of dwg_features;
  *     mlp_params is the device FP32 parameter blob of dwg_mlp_param_count() floats.
+ *   DWG_INIT_PCA: covariance (FP64) of p_i and its 16 nearest other points about their
+ *     mean; the unit eigenvector of its smallest eigenvalue, turned to point away from the
+ *     origin (n . p_i > 0; where n . p_i == 0, largest-magnitude component positive) --
+ *     the paper leaves the sign open; needs n > 16 and the workspace. An isotropic
+ *     neighbourhood gives (0, 0, 1) before the sign rule.
+ *   DWG_INIT_GAUSS: p_i / |p_i| (projection onto the unit sphere about the origin); a point
+ *     at the origin gets (0, 0, 1).
  *   N_out: output [3][n].
  */
 dwg_status dwg_init_normals(dwg_init_kind kind, uint64_t seed, const float* P, int64_t n,

@@ -206,3 +206,32 @@ def anchor_delta(P, k=10, n_anchor=4096, scale=1.0):
     skip = np.where(np.arange(n) % stride == 0, np.arange(n) // stride, -1).astype(np.int32)
     _, dist = knn(A, P, k, skip=skip)
     return scale * dist.mean(axis=1)
+
+
+def pca_normals(P, k=16):
+    """PCA initial normals (Sec. 5.1, "Normal Initialization"): the eigenvector (numpy eigh)
+    of the smallest eigenvalue of the covariance of p_i and its k nearest other points about
+    their mean. The paper leaves the sign open; this one points away from the origin
+    (n . p_i > 0), and where n . p_i == 0 makes the largest-magnitude component positive."""
+    P = _d(P)
+    n = P.shape[1]
+    idx, _ = knn_self(P, k)
+    nb = np.concatenate([np.arange(n)[:, None], idx], axis=1)  # [n, k+1]
+    X = P[:, nb].transpose(1, 2, 0)  # [n, k+1, 3]
+    X = X - X.mean(axis=1, keepdims=True)
+    C = np.einsum("nki,nkj->nij", X, X)
+    w, V = np.linalg.eigh(C)
+    v = V[:, :, 0]
+    s = np.sum(v * P.T, axis=1)
+    lead = v[np.arange(n), np.argmax(np.abs(v), axis=1)]
+    s = np.where(s == 0.0, lead, s)
+    return (v * np.where(s < 0, -1.0, 1.0)[:, None]).T
+
+
+def gauss_normals(P):
+    """Gauss-map initial normals (Sec. 5.1, "Normal Initialization"): p_i / |p_i|, the
+    projection onto the unit sphere about the origin; (0, 0, 1) at the origin."""
+    P = _d(P)
+    r = np.linalg.norm(P, axis=0)
+    out = np.where(r > 0, P / np.where(r > 0, r, 1.0), np.array([[0.0], [0.0], [1.0]]))
+    return out

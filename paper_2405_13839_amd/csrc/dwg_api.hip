@@ -244,13 +244,31 @@ dwg_status dwg_iterate(const float* P, const float* area, const float* delta, in
 dwg_status dwg_init_normals(dwg_init_kind kind, uint64_t seed, const float* P, int64_t n,
                             const float* mlp_params, float* N_out, void* ws, size_t ws_bytes,
                             void* stream) {
-  DWG_CHECK(kind == DWG_INIT_RANDOM || kind == DWG_INIT_MLP, "unknown init kind %d", (int)kind);
+  DWG_CHECK(kind == DWG_INIT_RANDOM || kind == DWG_INIT_MLP || kind == DWG_INIT_PCA || kind == DWG_INIT_GAUSS,
+            "unknown init kind %d", (int)kind);
   DWG_CHECK(N_out, "N_out must not be NULL");
   DWG_CHECK(n >= 1 && n < (int64_t(1) << 40), "n must be >= 1");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (kind == DWG_INIT_RANDOM) {
     DWG_PROPAGATE(check_device());
     return launch_random_normals(seed, n, N_out, st);
+  }
+  if (kind == DWG_INIT_GAUSS) {
+    DWG_CHECK(P, "P must not be NULL for DWG_INIT_GAUSS");
+    DWG_PROPAGATE(check_device());
+    return gauss_normals(P, n, N_out, st);
+  }
+  if (kind == DWG_INIT_PCA) {
+    DWG_CHECK(P, "P must not be NULL for DWG_INIT_PCA");
+    DWG_CHECK(n > kMaxK && n < (int64_t(1) << 31), "DWG_INIT_PCA needs %d < n < 2^31", kMaxK);
+    const size_t need = aux_bytes(n);
+    DWG_CHECK(ws || ws_bytes == 0, "ws is NULL but ws_bytes > 0");
+    if (!ws || ws_bytes < need) {
+      set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+      return DWG_E_WORKSPACE;
+    }
+    DWG_PROPAGATE(check_device());
+    return pca_normals(P, n, kMaxK, N_out, ws, st);
   }
   DWG_CHECK(P && mlp_params, "P and mlp_params must not be NULL for DWG_INIT_MLP");
   DWG_CHECK(n >= DWG_FEAT_K + 2, "DWG_INIT_MLP needs at least %d points", DWG_FEAT_K + 2);

@@ -162,6 +162,8 @@ dwg_status knn_run(const float* R, int64_t nr, const float* Q, int64_t m, int se
                    size_t ws_bytes, hipStream_t stream);
 dwg_status delta_from_knn(const float* dist, int64_t n, int k, float scale, float* delta,
                           hipStream_t stream);
+dwg_status pca_normals(const float* P, int64_t n, int k, float* N, void* ws, hipStream_t stream);
+dwg_status gauss_normals(const float* P, int64_t n, float* N, hipStream_t stream);
 dwg_status features_run(const float* P, int64_t n, int64_t n_anchor, float* feat, void* ws,
                         size_t ws_bytes, hipStream_t stream);
 dwg_status mlp_infer_run(const float* params, const float* X, int64_t B, float* Y, void* ws,

@@ -335,6 +335,114 @@ constexpr int kBboxBlocks = 256;
 
 int64_t max_cells_for(int64_t nr) { return std::max<int64_t>(8 * nr, 64); }
 
+// Unit eigenvector of the smallest eigenvalue of a symmetric 3x3 matrix (FP64): eigenvalues
+// by the trigonometric solution of the characteristic cubic (Smith, CACM 1961), the vector
+// as the largest cross product of two rows of (A - lambda I), sign left as it falls. An
+// isotropic matrix gives (0, 0, 1).
+__device__ void smallest_eigvec(const double a[6], double v[3]) {
+  const double a00 = a[0], a01 = a[1], a02 = a[2], a11 = a[3], a12 = a[4], a22 = a[5];
+  const double p1 = a01 * a01 + a02 * a02 + a12 * a12;
+  const double q = (a00 + a11 + a22) / 3.0;
+  const double p2 = (a00 - q) * (a00 - q) + (a11 - q) * (a11 - q) + (a22 - q) * (a22 - q) + 2.0 * p1;
+  const double p = sqrt(p2 / 6.0);
+  v[0] = 0.0;
+  v[1] = 0.0;
+  v[2] = 1.0;
+  if (!(p > 0.0)) return;
+  const double b00 = (a00 - q) / p, b11 = (a11 - q) / p, b22 = (a22 - q) / p;
+  const double b01 = a01 / p, b02 = a02 / p, b12 = a12 / p;
+  double r = 0.5 * (b00 * (b11 * b22 - b12 * b12) - b01 * (b01 * b22 - b12 * b02) + b02 * (b01 * b12 - b11 * b02));
+  r = fmin(1.0, fmax(-1.0, r));
+  const double phi = acos(r) / 3.0;
+  const double lam = q + 2.0 * p * cos(phi + 2.0943951023931954923);  // smallest
+  const double r0[3] = {a00 - lam, a01, a02}, r1[3] = {a01, a11 - lam, a12}, r2[3] = {a02, a12, a22 - lam};
+  double c[3][3];
+  const double* rows[3][2] = {{r0, r1}, {r0, r2}, {r1, r2}};
+  int best = 0;
+  double bn = -1.0;
+  for (int t = 0; t < 3; ++t) {
+    const double* x = rows[t][0];
+    const double* y = rows[t][1];
+    c[t][0] = x[1] * y[2] - x[2] * y[1];
+    c[t][1] = x[2] * y[0] - x[0] * y[2];
+    c[t][2] = x[0] * y[1] - x[1] * y[0];
+    const double nn = c[t][0] * c[t][0] + c[t][1] * c[t][1] + c[t][2] * c[t][2];
+    if (nn > bn) {
+      bn = nn;
+      best = t;
+    }
+  }
+  if (!(bn > 0.0)) return;
+  const double inv = 1.0 / sqrt(bn);
+  v[0] = c[best][0] * inv;
+  v[1] = c[best][1] * inv;
+  v[2] = c[best][2] * inv;
+}
+
+// PCA normals (Sec. 5.1 "Normal Initialization"): covariance of p_i and its k nearest other
+// points about their mean (FP64), eigenvector of the smallest eigenvalue, turned to point away
+// from the origin (n . p_i > 0; at n . p_i == 0 the largest-magnitude component positive).
+__global__ void k_pca_normals(const float* __restrict__ P, int64_t n, const int32_t* __restrict__ idx, int k,
+                              float* __restrict__ N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double mx = P[i], my = P[n + i], mz = P[2 * n + i];
+  for (int t = 0; t < k; ++t) {
+    const int64_t j = idx[i * k + t];
+    mx += P[j];
+    my += P[n + j];
+    mz += P[2 * n + j];
+  }
+  const double inv = 1.0 / (double)(k + 1);
+  mx *= inv;
+  my *= inv;
+  mz *= inv;
+  double a[6] = {0, 0, 0, 0, 0, 0};
+  for (int t = -1; t < k; ++t) {
+    const int64_t j = t < 0 ? i : (int64_t)idx[i * k + t];
+    const double x = P[j] - mx, y = P[n + j] - my, z = P[2 * n + j] - mz;
+    a[0] += x * x;
+    a[1] += x * y;
+    a[2] += x * z;
+    a[3] += y * y;
+    a[4] += y * z;
+    a[5] += z * z;
+  }
+  double v[3];
+  smallest_eigvec(a, v);
+  double s = v[0] * P[i] + v[1] * P[n + i] + v[2] * P[2 * n + i];
+  if (s == 0.0) {
+    const double m0 = fabs(v[0]), m1 = fabs(v[1]), m2 = fabs(v[2]);
+    s = (m0 >= m1 && m0 >= m2) ? v[0] : (m1 >= m2 ? v[1] : v[2]);
+  }
+  if (s < 0.0) {
+    v[0] = -v[0];
+    v[1] = -v[1];
+    v[2] = -v[2];
+  }
+  N[i] = (float)v[0];
+  N[n + i] = (float)v[1];
+  N[2 * n + i] = (float)v[2];
+}
+
+// Gauss map (Sec. 5.1 "Normal Initialization"): n_i = p_i / |p_i| (about the origin);
+// a point at the origin gets (0, 0, 1).
+__global__ void k_gauss_normals(const float* __restrict__ P, int64_t n, float* __restrict__ N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double x = P[i], y = P[n + i], z = P[2 * n + i];
+  const double r = sqrt(x * x + y * y + z * z);
+  if (r > 0.0) {
+    N[i] = (float)(x / r);
+    N[n + i] = (float)(y / r);
+    N[2 * n + i] = (float)(z / r);
+  } else {
+    N[i] = 0.0f;
+    N[n + i] = 0.0f;
+    N[2 * n + i] = 1.0f;
+  }
+}
+
 unsigned grid_for(int64_t n, int block = 256, int64_t cap = 65535) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, block), cap));
 }
@@ -470,6 +578,23 @@ size_t carve_anchor(Carver& c, int64_t n, int64_t chunk, int64_t n_anchor, Ancho
   carve_knn(c, x.na, &x.w);
   if (out) *out = x;
   return c.used - s0;
+}
+
+dwg_status pca_normals(const float* P, int64_t n, int k, float* N, void* ws, hipStream_t stream) {
+  Carver c(ws);
+  int32_t* idx = c.take<int32_t>((size_t)n * k);
+  float* dist = c.take<float>((size_t)n * k);
+  dwg_status s = knn_run(P, n, P, n, 1, nullptr, k, idx, dist, static_cast<char*>(ws) + c.used, 0, stream);
+  if (s != DWG_OK) return s;
+  hipLaunchKernelGGL(k_pca_normals, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, stream, P, n, idx, k, N);
+  DWG_TRY_LAUNCH();
+  return DWG_OK;
+}
+
+dwg_status gauss_normals(const float* P, int64_t n, float* N, hipStream_t stream) {
+  hipLaunchKernelGGL(k_gauss_normals, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, stream, P, n, N);
+  DWG_TRY_LAUNCH();
+  return DWG_OK;
 }
 
 // Anchors: every stride-th point, stride = max(1, n / n_anchor); grid over the anchors.

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libdwg.so")
 
 DWG_OK, DWG_NOT_CONVERGED = 0, 1
 DWG_E_INVALID, DWG_E_WORKSPACE, DWG_E_DEVICE, DWG_E_NONFINITE, DWG_E_UNSUPPORTED = -1, -2, -3, -4, -5
-INIT_RANDOM, INIT_MLP = 0, 1
+INIT_RANDOM, INIT_MLP, INIT_PCA, INIT_GAUSS = 0, 1, 2, 3
 MLP_IN, MLP_HID, MLP_OUT, FEAT_K = 48, 128, 3, 16
 
 
@@ -203,6 +203,30 @@ def random_normals(n: int, seed: int, device) -> torch.Tensor:
     N = torch.empty((3, n), dtype=torch.float32, device=device)
     _check(lib.dwg_init_normals(INIT_RANDOM, ctypes.c_uint64(seed), None, n, None, _ptr(N), None, 0,
                                 _stream(N.device)))
+    return N
+
+
+def pca_normals(P, ws=None) -> torch.Tensor:
+    """Smallest-eigenvalue eigenvector of each point's 16-NN covariance, [3, n]."""
+    lib = load()
+    P = _dev(P, "P")
+    n = P.shape[1]
+    if ws is None:
+        ws = workspace(n, n, P.device)
+    N = torch.empty((3, n), dtype=torch.float32, device=P.device)
+    _check(lib.dwg_init_normals(INIT_PCA, ctypes.c_uint64(0), _ptr(P), n, None, _ptr(N), _ptr(ws), ws.numel(),
+                                _stream(P.device)))
+    return N
+
+
+def gauss_normals(P) -> torch.Tensor:
+    """Gauss map p / |p|, [3, n]."""
+    lib = load()
+    P = _dev(P, "P")
+    n = P.shape[1]
+    N = torch.empty((3, n), dtype=torch.float32, device=P.device)
+    _check(lib.dwg_init_normals(INIT_GAUSS, ctypes.c_uint64(0), _ptr(P), n, None, _ptr(N), None, 0,
+                                _stream(P.device)))
     return N
 
 

@@ -275,3 +275,37 @@ def test_anchor_delta_against_kdtree():
     is_anchor = np.arange(5000) % stride == 0
     ref = np.where(is_anchor, dd[:, 1:].mean(axis=1), dd[:, :10].mean(axis=1)) * 1.5
     np.testing.assert_allclose(d, ref, rtol=1e-12)
+
+
+def test_pca_normals_plane_closed_form():
+    """Sec. 5.1 PCA init: points on the plane z = 0.5 + 0.3 x - 0.2 y (off the origin, so a
+    covariance taken about the origin instead of the mean fails) have the plane normal
+    (-0.3, 0.2, 1)/|.| as the smallest-eigenvalue eigenvector, turned away from the origin."""
+    rng = np.random.default_rng(3)
+    x, y = rng.uniform(-1, 1, (2, 500))
+    P = np.stack([x, y, 0.5 + 0.3 * x - 0.2 * y])
+    N = oracle.pca_normals(P, 16)
+    ref = np.array([-0.3, 0.2, 1.0]) / math.sqrt(1.13)
+    np.testing.assert_allclose(N, np.repeat(ref[:, None], 500, axis=1), atol=1e-9)
+    # the mirrored plane z = -0.5 - 0.3 x + 0.2 y lies below the origin: its normal turns down
+    N2 = oracle.pca_normals(P * np.array([[1.0], [1.0], [-1.0]]), 16)
+    ref2 = np.array([-0.3, 0.2, -1.0]) / math.sqrt(1.13)
+    np.testing.assert_allclose(N2, np.repeat(ref2[:, None], 500, axis=1), atol=1e-9)
+
+
+def test_pca_normals_sphere_is_outward_radial(fib):
+    """On a dense sphere about the origin the smallest-variance direction of a 16-NN patch is
+    the radius, to O(h) of the patch size (the largest eigenvector would be tangent), and the
+    sign rule turns every one outward."""
+    N = oracle.pca_normals(fib.P, 16)
+    c = np.sum(N * fib.N_true, axis=0)
+    assert c.min() > 0.999
+
+
+def test_gauss_normals_sphere_exact():
+    """Sec. 5.1 Gauss map: on a sphere about the origin p / |p| is the outward normal; the
+    origin itself maps to (0, 0, 1)."""
+    s = synth.fibonacci_sphere(1000)
+    P = s.P * 2.5
+    np.testing.assert_allclose(oracle.gauss_normals(P), s.N_true, atol=1e-6)
+    np.testing.assert_array_equal(oracle.gauss_normals(np.zeros((3, 1))), [[0.0], [0.0], [1.0]])
