@@ -6,7 +6,8 @@ against. Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg o
 calls it; the GPU library never imports this package.
 
 The arithmetic lives in ``dwg_oracle.c`` (plain C, double precision, Neumaier sums,
-OpenMP over independent queries) and ``mlp.py`` (NumPy float64). This module is the
+OpenMP over independent queries), ``tree_oracle.c`` (the octree evaluation of Sec. 5.2)
+and ``mlp.py`` (NumPy float64). This module is the
 ctypes binding: it promotes the caller's FP32 arrays exactly to float64 and returns
 float64 results.
 
@@ -23,15 +24,16 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dwg_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "tree_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
 def build(force: bool = False) -> str:
-    """Compile dwg_oracle.c with gcc (-O2 -fopenmp, no fast-math) into liboracle.so."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile the oracle's C sources with gcc (-O2 -fopenmp, no fast-math) into liboracle.so."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(s) for s in _SRCS):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-Wall", "-o", tmp, _SRC, "-lm"]
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-Wall", "-o", tmp, *_SRCS, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -59,6 +61,11 @@ def _load():
         lib.orc_splitmix64.restype = ctypes.c_uint64
         lib.orc_random_normals.argtypes = [ctypes.c_uint64, i64, dp]
         lib.orc_num_threads.restype = ctypes.c_int
+        lp = ctypes.POINTER(ctypes.c_int64)
+        lib.orc_octree.argtypes = [dp, i64, ctypes.c_int, lp, lp, i64]
+        lib.orc_octree.restype = i64
+        lib.orc_tree_gwn.argtypes = [dp, dp, dp, dp, i64, dp, i64, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_int, dp, dp, ip, lp]
         _lib = lib
     return _lib
 
@@ -235,3 +242,46 @@ def gauss_normals(P):
     r = np.linalg.norm(P, axis=0)
     out = np.where(r > 0, P / np.where(r > 0, r, 1.0), np.array([[0.0], [0.0], [1.0]]))
     return out
+
+
+TREE_DEPTH = 21
+
+
+def octree(P, leaf=16):
+    """Octree of Sec. 5.2 as built by tree_oracle.c: (perm int64 [n], info int64 [nodes, 4] =
+    (start, end, level, skip) in depth-first pre-order)."""
+    lib = _load()
+    P = _d(P)
+    n = P.shape[1]
+    perm = np.zeros(n, dtype=np.int64)
+    cap = max(64, 4 * n)
+    while True:
+        info = np.zeros((cap, 4), dtype=np.int64)
+        cnt = lib.orc_octree(_p(P), n, int(leaf), _p(perm, ctypes.c_int64), _p(info, ctypes.c_int64), cap)
+        if cnt < 0:
+            raise ValueError("orc_octree rejected its arguments")
+        if cnt <= cap:
+            return perm, info[:cnt].copy()
+        cap = int(cnt)
+
+
+def tree_gwn(P, N, area, delta, Q, lam=0.0, eps=0.0, beta=2.3, leaf=16, grad=True, visits=False):
+    """Octree-approximated w [m], grad w [3,m] (or None), flags [m] (and visited-node counts
+    [m] when visits=True): Sec. 5.2 traversal with opening radius max(beta r, r + dmax)."""
+    lib = _load()
+    P = _d(P)
+    n = P.shape[1]
+    N = _d(N, (3, n))
+    area = _d(area, (n,))
+    delta = None if delta is None else _d(delta, (n,))
+    Q = _d(Q)
+    m = Q.shape[1]
+    w = np.zeros(m)
+    g = np.zeros((3, m)) if grad else None
+    fl = np.zeros(m, dtype=np.int32)
+    vis = np.zeros(m, dtype=np.int64)
+    rc = lib.orc_tree_gwn(_p(P), _p(N), _p(area), _p(delta), n, _p(Q), m, float(lam), float(eps), float(beta),
+                          int(leaf), _p(w), _p(g), _p(fl, ctypes.c_int32), _p(vis, ctypes.c_int64))
+    if rc != 0:
+        raise ValueError("orc_tree_gwn rejected its arguments")
+    return (w, g, fl, vis) if visits else (w, g, fl)

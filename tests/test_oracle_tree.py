@@ -1,0 +1,122 @@
+"""Pins of the octree oracle (Sec. 5.2 "Octree Traversal") against facts that do not come
+from its own code: the exact all-pairs sum (an opening radius that opens every node), an
+octree built by explicit geometric subdivision, the far-field error falling with the
+opening factor, and the area-weighted dipole of a far cluster."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_13839_amd import synth
+
+
+def _cloud(n, seed):
+    rng = np.random.default_rng(seed)
+    P = (rng.uniform(-1, 1, (3, n)) * np.array([[1.0], [0.6], [0.3]])).astype(np.float32)
+    N = rng.normal(size=(3, n))
+    N = (N / np.linalg.norm(N, axis=0)).astype(np.float32)
+    a = rng.uniform(0.5, 1.5, n).astype(np.float32) * np.float32(4.0 / n)
+    d = rng.uniform(0.0, 0.05, n).astype(np.float32)
+    return P, N, a, d
+
+
+@pytest.mark.parametrize("lam", [0.0, 10.0])
+@pytest.mark.parametrize("leaf", [1, 16])
+def test_tree_opening_everything_is_exact(lam, leaf):
+    """beta -> infinity opens every node: the traversal then sums every point exactly once
+    with the modified kernel, which is the all-pairs definition."""
+    P, N, a, d = _cloud(3000, 1)
+    Q = np.concatenate([P[:, :200], np.random.default_rng(2).uniform(-1.2, 1.2, (3, 50))], axis=1)
+    w, g, _ = oracle.gwn(P, N, a, d, Q, lam=lam)
+    wt, gt, _ = oracle.tree_gwn(P, N, a, d, Q, lam=lam, beta=1e30, leaf=leaf)
+    assert np.abs(wt - w).max() <= 1e-12 * max(1.0, np.abs(w).max())
+    assert np.abs(gt - g).max() <= 1e-12 * max(1.0, np.abs(g).max())
+
+
+def _geometric_octree(P, leaf, depth=21):
+    """Nodes as (level, sorted point indices) by explicit recursive subdivision of the cube."""
+    P = np.asarray(P, np.float64)
+    lo = P.min(axis=1)
+    ext = (P.max(axis=1) - lo).max()
+    out = []
+
+    def rec(idx, level, cell):
+        out.append((level, tuple(sorted(idx))))
+        if len(idx) <= leaf or level == depth:
+            return
+        h = ext / 2 ** (level + 1)
+        kids = {}
+        for i in idx:
+            c = tuple(int(min(max(math.floor((P[d, i] - lo[d]) / h), 0), 2 ** (level + 1) - 1)) for d in range(3))
+            kids.setdefault(c, []).append(i)
+        for c in sorted(kids, key=lambda c: [((c[0] >> b) & 1, (c[1] >> b) & 1, (c[2] >> b) & 1)
+                                            for b in range(level, -1, -1)]):
+            rec(kids[c], level + 1, c)
+
+    rec(list(range(P.shape[1])), 0, (0, 0, 0))
+    return out
+
+
+@pytest.mark.parametrize("n,leaf", [(1, 1), (7, 1), (300, 4), (2000, 16)])
+def test_octree_matches_geometric_subdivision(n, leaf):
+    P = _cloud(n, 3 + n)[0]
+    perm, info = oracle.octree(P, leaf)
+    ref = _geometric_octree(P, leaf)
+    assert len(info) == len(ref)
+    for (s, e, lev, skip), (rl, ri) in zip(info, ref):
+        assert lev == rl and tuple(sorted(perm[s:e])) == ri
+    # pre-order: skip is the index just past the subtree; children tile the parent's range
+    assert sorted(perm.tolist()) == list(range(n))
+    for k, (s, e, lev, skip) in enumerate(info):
+        assert skip > k and (skip == len(info) or info[skip][0] >= e)
+        c, pos = k + 1, s
+        while c < skip:
+            assert info[c][2] == lev + 1 and info[c][0] == pos
+            pos = info[c][1]
+            c = info[c][3]
+        assert skip == k + 1 or pos == e
+
+
+def test_tree_error_falls_with_beta():
+    """Exact outward normals on a sphere: w = 1 inside, 0 outside. The node-dipole (order-0)
+    far field has an error that shrinks as the opening factor grows."""
+    s = synth.fibonacci_sphere(20000)
+    Q = np.array([[0, 0, 0], [0.3, 0.2, -0.1], [1.5, 0, 0], [0, 2, 0]], dtype=np.float64).T
+    truth = np.array([1.0, 1.0, 0.0, 0.0])
+    err = []
+    for beta in [2.3, 4.0, 8.0]:
+        w, _, _ = oracle.tree_gwn(s.P, s.N_true, s.area, None, Q, beta=beta)
+        err.append(np.abs(w - truth).max())
+    assert err[0] <= 0.03 and err[1] < err[0] and err[2] < err[1], err
+
+
+def test_far_cluster_is_area_weighted_dipole():
+    """A far node stands for one dipole: moment sum a_j n_j at the area-weighted centre."""
+    P = np.array([[0.0, 0.01, 0.0], [0.0, 0.0, 0.02], [0.0, 0.0, 0.0]])
+    N = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 0.0], [1.0, 1.0, 1.0]])
+    a = np.array([1.0, 2.0, 5.0])
+    q = np.array([[0.3], [0.1], [2.0]])
+    w, _, _ = oracle.tree_gwn(P, N, a, None, q, beta=2.3, leaf=1)
+    cm = (P * a).sum(axis=1) / a.sum()
+    d = cm - q[:, 0]
+    ref = a.sum() * d[2] / (4 * math.pi * np.linalg.norm(d) ** 3)
+    assert abs(w[0] - ref) <= 1e-14 * abs(ref)
+    d0 = P.mean(axis=1) - q[:, 0]  # unweighted centre: visibly different
+    assert abs(a.sum() * d0[2] / (4 * math.pi * np.linalg.norm(d0) ** 3) - ref) > 1e-6 * abs(ref)
+
+
+def test_far_test_keeps_the_clamp():
+    """Two points 10 apart with radius 1 and a query 0.5 from one of them: the near point
+    is opened and clamped (its distance is inside its radius), the other counts as a far
+    single-point node, which is exact -- so the octree value equals the all-pairs value."""
+    P = np.array([[0.0, 10.0], [0.0, 0.0], [0.0, 0.0]])
+    N = np.array([[1.0, 0.0], [0.0, 1.0], [0.0, 0.0]])
+    a = np.array([1.0, 1.0])
+    d = np.array([1.0, 1.0])
+    q = np.array([[0.3], [0.4], [0.0]])
+    for lam in [0.0, 10.0]:
+        w, g, _ = oracle.gwn(P, N, a, d, q, lam=lam)
+        wt, gt, _ = oracle.tree_gwn(P, N, a, d, q, lam=lam, beta=2.3, leaf=1)
+        np.testing.assert_allclose(wt, w, rtol=1e-14)
+        np.testing.assert_allclose(gt, g, rtol=1e-14, atol=1e-300)
