@@ -41,13 +41,17 @@ typedef enum dwg_status {
   DWG_E_UNSUPPORTED = -5  /* the device is not gfx950 */
 } dwg_status;
 
-/* Kernel parameters (Sec. 4.2 Eq. 5 screening; Sec. 5.2 modified Poisson kernel). */
+/* Kernel parameters (Sec. 4.2 Eq. 5 screening; Sec. 5.2 modified Poisson kernel and
+ * octree traversal). */
 typedef struct dwg_kernel_params {
   float lambda;    /* screening coefficient >= 0; 0 = plain GWN (Eq. 2-3) */
   float eps;       /* >= 0: global floor on the kernel radius (the "small constant") */
   int compensated; /* 1 = Kahan-compensated accumulation of per-tile partial sums */
-  int split;       /* source splits: 0 = automatic, else 1..64 */
-  int reserved[4]; /* must be zero */
+  int split;       /* all-pairs source splits: 0 = automatic, else 1..64 */
+  float tree_beta; /* 0 = exact all-pairs sum; >= 1 = octree traversal (Sec. 5.2) with
+                      opening radius max(tree_beta * r, r + dmax) per node (paper: 2.3) */
+  int tree_leaf;   /* octree leaf capacity: 0 = 16, else 1..1024 */
+  int reserved[2]; /* must be zero */
 } dwg_kernel_params;
 
 /* Iteration parameters (Algorithm 1; Sec. 5.1 "Model-independent Parameters"). */
@@ -112,6 +116,33 @@ dwg_status dwg_gwn_grad(const float* P, const float* N, const float* area, const
                         int64_t n, const float* Q, int64_t m, const dwg_kernel_params* kp,
                         float* w, float* grad, double* wmean, void* ws, size_t ws_bytes,
                         void* stream);
+
+/*
+ * Octree mode (tree_beta > 0; Sec. 5.2 "Octree Traversal"). The sources are put in an
+ * octree: root = the cube over their bounding box (side = the largest extent), cells down
+ * to level 21 (Morton order of floor((x - lo) 2^21 / side), FP64), a node = a non-empty cell,
+ * a leaf when it holds <= tree_leaf sources or sits at level 21; a cell whose sources all
+ * lie in one child is represented by the deepest cell of that chain. Per node: area A,
+ * centre c.m = sum a p / A, r = max |p - c.m|, dmax = max max(delta_j, eps), moment
+ * M = sum a n. For each query, depth-first from the root: a node with
+ * |q - c.m| > max(tree_beta r, r + dmax) counts as one dipole M at c.m (kernel without
+ * clamp); otherwise its children are visited, or, at a leaf, its sources are summed one by
+ * one exactly as in the all-pairs definition. Requires n < 2^30. The result approximates
+ * the all-pairs sum (tree_beta -> infinity gives it back); `split` is ignored.
+ */
+
+/*
+ * dwg_octree -- the octree of the octree mode for P [3][n] with leaf capacity `leaf`
+ * (0 = 16). Synchronous. Outputs: perm [n] int32 (i-th source in Morton order); nodes
+ * [cap][4] int32 = (start, end, level, skip) per node in depth-first pre-order, where
+ * [start, end) is the node's range of sorted positions and skip the index of the first node
+ * after its subtree; *count (HOST) = number of nodes, at most 2n - 1 (cap >= 2n always
+ * suffices). Workspace: dwg_workspace_bytes(n, n, kp) for any kp with tree_beta > 0.
+ * Errors: DWG_E_INVALID (NULL pointers, n < 1 or >= 2^30, leaf outside 0..1024, count > cap
+ * -- *count is still set), DWG_E_WORKSPACE, DWG_E_DEVICE.
+ */
+dwg_status dwg_octree(const float* P, int64_t n, int leaf, int32_t* perm, int32_t* nodes, int64_t cap,
+                      int64_t* count, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * dwg_iterate -- Algorithm 1 with every input point as a query (Sec. 4.3). Synchronous.

@@ -12,7 +12,10 @@
  * the bits of (cx, cy, cz) with x the most significant of each triple. Points are ordered
  * by (code, index). A node is a non-empty cell; it is a leaf when it holds at most
  * `leaf` points or sits at level D, otherwise its non-empty children (in Morton order)
- * are nodes. Nodes are numbered in depth-first pre-order.
+ * are nodes. A cell whose points all lie in one child cell is not a node of its own: it
+ * holds exactly the points of that child, so every summary below and every decision of
+ * the traversal would be the same for both; the deepest cell of such a chain is kept.
+ * Nodes are numbered in depth-first pre-order.
  *
  * Node summary (Sec. 5.2): area A = sum a_j; mass centre c.m = sum a_j p_j / A (the first
  * point of the node when A == 0); r = the largest |p_j - c.m|; moment M = sum a_j n_j (the
@@ -83,7 +86,14 @@ static int64_t new_node(tbuild* t) {
   return t->count++;
 }
 
+/* true when every point of [s, e) lies in the same cell of level `level` */
+static int one_cell(const tbuild* t, int64_t s, int64_t e, int level) {
+  const int sh = 3 * (TREE_DEPTH - level);
+  return (t->code[s] >> sh) == (t->code[e - 1] >> sh);
+}
+
 static int64_t build(tbuild* t, int64_t s, int64_t e, int level) {
+  while (e - s > t->leaf && level < TREE_DEPTH && one_cell(t, s, e, level + 1)) ++level;
   const int64_t k = new_node(t);
   t->nodes[k].start = s;
   t->nodes[k].end = e;

@@ -39,7 +39,11 @@ namespace {
     if (s_ != DWG_OK) return s_;    \
   } while (0)
 
-const dwg_kernel_params kDefaultKp = {0.0f, 0.0f, 1, 0, {0, 0, 0, 0}};
+const dwg_kernel_params kDefaultKp = {0.0f, 0.0f, 1, 0, 0.0f, 0, {0, 0}};
+constexpr int kDefaultLeaf = 16;
+
+bool tree_mode(const dwg_kernel_params& kp) { return kp.tree_beta > 0.0f; }
+int tree_leaf(const dwg_kernel_params& kp) { return kp.tree_leaf > 0 ? kp.tree_leaf : kDefaultLeaf; }
 
 dwg_status check_kp(const dwg_kernel_params* kp) {
   if (!kp) return DWG_OK;
@@ -47,7 +51,10 @@ dwg_status check_kp(const dwg_kernel_params* kp) {
   DWG_CHECK(std::isfinite(kp->eps) && kp->eps >= 0.0f, "eps must be finite and >= 0");
   DWG_CHECK(kp->compensated == 0 || kp->compensated == 1, "compensated must be 0 or 1");
   DWG_CHECK(kp->split >= 0 && kp->split <= kMaxSplit, "split must be in [0, 64]");
-  for (int i = 0; i < 4; ++i) DWG_CHECK(kp->reserved[i] == 0, "reserved fields must be zero");
+  DWG_CHECK(std::isfinite(kp->tree_beta) && (kp->tree_beta == 0.0f || kp->tree_beta >= 1.0f),
+            "tree_beta must be 0 (all pairs) or a finite value >= 1");
+  DWG_CHECK(kp->tree_leaf >= 0 && kp->tree_leaf <= 1024, "tree_leaf must be in [0, 1024]");
+  for (int i = 0; i < 2; ++i) DWG_CHECK(kp->reserved[i] == 0, "reserved fields must be zero");
   return DWG_OK;
 }
 
@@ -101,8 +108,46 @@ struct EventPair {
 
 size_t gwn_bytes(int64_t n_src, int64_t n_qry, const dwg_kernel_params& kp) {
   Carver c(nullptr);
-  carve_gwn(c, n_src, n_qry, choose_split(n_src, n_qry, kp.split), false, nullptr);
+  if (tree_mode(kp)) {
+    carve_gwn(c, n_src, n_qry, 1, false, nullptr);
+    carve_tree(c, n_src, tree_leaf(kp), kp.tree_beta, nullptr);
+  } else {
+    carve_gwn(c, n_src, n_qry, choose_split(n_src, n_qry, kp.split), false, nullptr);
+  }
   return c.used;
+}
+
+// Carves the evaluation state, orders sources and queries and stages the sources: the
+// all-pairs tiles, or the octree with its node summaries.
+struct EvalState {
+  GwnWork wk;
+  TreeWork tw;
+  bool tree = false;
+};
+
+dwg_status eval_prepare(const float* P, const float* N, const float* area, const float* delta, int64_t n,
+                        const float* Q, int64_t m, const dwg_kernel_params& kp, bool same, void* ws,
+                        hipStream_t st, EvalState* es) {
+  Carver c(ws);
+  es->tree = tree_mode(kp);
+  if (!es->tree) {
+    carve_gwn(c, n, m, choose_split(n, m, kp.split), same, &es->wk);
+    DWG_PROPAGATE(launch_order(P, n, delta, kp.eps, Q, m, same, es->wk, st));
+    return launch_stage(P, N, area, delta, n, kp.eps, es->wk, st);
+  }
+  carve_gwn(c, n, m, 1, same, &es->wk);
+  carve_tree(c, n, tree_leaf(kp), kp.tree_beta, &es->tw);
+  DWG_PROPAGATE(tree_build(P, area, delta, n, kp.eps, es->tw, es->wk.perm_s, st));
+  if (!same) DWG_PROPAGATE(spatial_sort(Q, m, nullptr, 0.0f, es->wk.sort, es->wk.perm_q, st));
+  return launch_stage(P, N, area, delta, n, kp.eps, es->wk, st);
+}
+
+// w (and grad) at the sorted queries into the per-query partials.
+dwg_status eval_run(const float* Q, int64_t m, const dwg_kernel_params& kp, bool grad, const EvalState& es,
+                    hipStream_t st) {
+  if (!es.tree) return launch_gwn(Q, m, kp, grad, es.wk, st);
+  DWG_PROPAGATE(tree_moments(es.wk, es.tw, st));
+  return tree_eval(Q, m, kp, grad, es.wk, es.tw, st);
 }
 
 dwg_status gwn_common(const float* P, const float* N, const float* area, const float* delta,
@@ -115,6 +160,7 @@ dwg_status gwn_common(const float* P, const float* N, const float* area, const f
   DWG_CHECK(grad ? (g != nullptr) : (w != nullptr), grad ? "grad must not be NULL" : "w must not be NULL");
   DWG_PROPAGATE(check_kp(kpp));
   const dwg_kernel_params kp = kpp ? *kpp : kDefaultKp;
+  DWG_CHECK(!tree_mode(kp) || n < (int64_t(1) << 30), "octree mode needs n < 2^30");
   const size_t need = gwn_bytes(n, m, kp);
   DWG_CHECK(ws || ws_bytes == 0, "ws is NULL but ws_bytes > 0");
   if (!ws || ws_bytes < need) {
@@ -123,14 +169,11 @@ dwg_status gwn_common(const float* P, const float* N, const float* area, const f
   }
   DWG_PROPAGATE(check_device());
   hipStream_t st = static_cast<hipStream_t>(stream);
-  Carver c(ws);
-  GwnWork wk;
+  EvalState es;
   const bool same = (Q == P && m == n);
-  carve_gwn(c, n, m, choose_split(n, m, kp.split), same, &wk);
-  DWG_PROPAGATE(launch_order(P, n, delta, kp.eps, Q, m, same, wk, st));
-  DWG_PROPAGATE(launch_stage(P, N, area, delta, n, kp.eps, wk, st));
-  DWG_PROPAGATE(launch_gwn(Q, m, kp, grad, wk, st));
-  DWG_PROPAGATE(launch_combine(m, kp, grad, w, g, wmean, wk, st));
+  DWG_PROPAGATE(eval_prepare(P, N, area, delta, n, Q, m, kp, same, ws, st, &es));
+  DWG_PROPAGATE(eval_run(Q, m, kp, grad, es, st));
+  DWG_PROPAGATE(launch_combine(m, kp, grad, w, g, wmean, es.wk, st));
   return DWG_OK;
 }
 
@@ -191,6 +234,7 @@ dwg_status dwg_iterate(const float* P, const float* area, const float* delta, in
   DWG_CHECK(ip->top_frac > 0.0 && ip->top_frac <= 1.0, "top_frac must be in (0, 1]");
   DWG_PROPAGATE(check_kp(kpp));
   const dwg_kernel_params kp = kpp ? *kpp : kDefaultKp;
+  DWG_CHECK(!tree_mode(kp) || n < (int64_t(1) << 30), "octree mode needs n < 2^30");
   const size_t need = gwn_bytes(n, n, kp);
   DWG_CHECK(ws || ws_bytes == 0, "ws is NULL but ws_bytes > 0");
   if (!ws || ws_bytes < need) {
@@ -199,17 +243,15 @@ dwg_status dwg_iterate(const float* P, const float* area, const float* delta, in
   }
   DWG_PROPAGATE(check_device());
   hipStream_t st = static_cast<hipStream_t>(stream);
-  Carver c(ws);
-  GwnWork wk;
-  carve_gwn(c, n, n, choose_split(n, n, kp.split), true, &wk);
-  DWG_PROPAGATE(launch_order(P, n, delta, kp.eps, P, n, true, wk, st));
-  DWG_PROPAGATE(launch_stage(P, N_inout, area, delta, n, kp.eps, wk, st));
+  EvalState es;
+  DWG_PROPAGATE(eval_prepare(P, N_inout, area, delta, n, P, n, kp, true, ws, st, &es));
+  const GwnWork& wk = es.wk;
   EventPair ev;
   DWG_PROPAGATE(ev.create());
   dwg_status result = DWG_NOT_CONVERGED;
   for (int t = 0; t < ip->max_iters; ++t) {
     DWG_TRY_HIP(hipEventRecord(ev.a, st));
-    DWG_PROPAGATE(launch_gwn(P, n, kp, true, wk, st));
+    DWG_PROPAGATE(eval_run(P, n, kp, true, es, st));
     DWG_TRY_HIP(hipEventRecord(ev.b, st));
     DWG_PROPAGATE(launch_update(n, kp, N_inout, wk, st));
     DWG_PROPAGATE(launch_stats(n, ip->top_frac, wk, st));
@@ -239,6 +281,33 @@ dwg_status dwg_iterate(const float* P, const float* area, const float* delta, in
   }
   if (ip->fixed_iters) result = DWG_OK;
   return result;
+}
+
+dwg_status dwg_octree(const float* P, int64_t n, int leaf, int32_t* perm, int32_t* nodes, int64_t cap,
+                      int64_t* count, void* ws, size_t ws_bytes, void* stream) {
+  if (count) *count = 0;
+  DWG_CHECK(P && perm && nodes && count, "P, perm, nodes and count must not be NULL");
+  DWG_CHECK(n >= 1 && n < (int64_t(1) << 30), "n must be in [1, 2^30)");
+  DWG_CHECK(leaf >= 0 && leaf <= 1024, "leaf must be in [0, 1024]");
+  DWG_CHECK(cap >= 1, "cap must be >= 1");
+  dwg_kernel_params kp = kDefaultKp;
+  kp.tree_beta = 2.3f;
+  kp.tree_leaf = leaf;
+  const size_t need = gwn_bytes(n, n, kp);
+  DWG_CHECK(ws || ws_bytes == 0, "ws is NULL but ws_bytes > 0");
+  if (!ws || ws_bytes < need) {
+    set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+    return DWG_E_WORKSPACE;
+  }
+  DWG_PROPAGATE(check_device());
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Carver c(ws);
+  GwnWork wk;
+  TreeWork tw;
+  carve_gwn(c, n, n, 1, true, &wk);
+  carve_tree(c, n, tree_leaf(kp), kp.tree_beta, &tw);
+  DWG_PROPAGATE(tree_build(P, nullptr, nullptr, n, 0.0f, tw, perm, st));
+  return tree_export(tw, nodes, cap, count, st);
 }
 
 dwg_status dwg_init_normals(dwg_init_kind kind, uint64_t seed, const float* P, int64_t n,

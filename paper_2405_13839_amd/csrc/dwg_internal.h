@@ -137,6 +137,47 @@ struct GwnWork {
 
 size_t carve_gwn(Carver& c, int64_t n_src, int64_t n_qry, int split, bool same, GwnWork* out);
 
+// Octree of the sources for the Sec. 5.2 traversal (dwg_tree.hip): Morton-sorted sources,
+// nodes in depth-first pre-order, node summaries; carved from the workspace.
+struct TreeWork {
+  float* bpart;              // [kBboxParts] bbox partials
+  float* box;                // [8] bbox
+  double* frame;             // [4] lo xyz, 2^21 / extent
+  uint64_t* key[2];          // [n] Morton codes (radix-sort ping-pong)
+  int32_t* val[2];           // [n] source indices (ping-pong)
+  int32_t* hist;             // [256 * nsb + 1] radix digit counts
+  int32_t* hsums;            // scan tile totals
+  int32_t* lev;              // [n] level range of the nodes starting at each sorted source
+  int32_t* off;              // [n + 1] node offsets; off[n] = node count
+  int32_t* osums;
+  int4* node;                // [cap] start, end, skip, level | leaf << 8
+  double4* geo;              // [cap] centre xyz, squared opening radius
+  float4* mom;               // [cap] moment sum a n / 4 pi
+  unsigned long long* rbits; // [cap] node radius (FP64 bits)
+  uint32_t* dbits;           // [cap] largest kernel radius (FP32 bits)
+  int32_t* coff;             // [cap + 1] chunk offsets (chunks of 256 sorted sources per node)
+  int32_t* csums;
+  double4* csum;             // [ccap] per-chunk FP64 sums of a, a px, a py, a pz
+  double* scan;              // [3][n + 1] FP64 prefix sums of the staged moments
+  double* sblk;              // [3][nscan] block totals
+  int64_t n, cap, ccap, nsb, nscan;
+  int leaf;
+  double beta;
+};
+int64_t tree_cap(int64_t n);
+size_t carve_tree(Carver& c, int64_t n, int leaf, double beta, TreeWork* out);
+// Sorts the sources (perm[i] = index of the i-th sorted source) and builds the nodes; with
+// area != NULL also the node centres, radii and opening radii.
+dwg_status tree_build(const float* P, const float* area, const float* delta, int64_t n, float eps,
+                      const TreeWork& t, int32_t* perm, hipStream_t st);
+// Node moments from the staged sources of w (call after every restaging).
+dwg_status tree_moments(const GwnWork& w, const TreeWork& t, hipStream_t st);
+// Octree-approximated w (and grad) at the sorted queries of w into w.part (split 1).
+dwg_status tree_eval(const float* Q, int64_t m, const dwg_kernel_params& kp, bool grad, const GwnWork& w,
+                     const TreeWork& t, hipStream_t st);
+dwg_status tree_export(const TreeWork& t, int32_t* nodes_out, int64_t cap_out, int64_t* count_host,
+                       hipStream_t st);
+
 // Workspace bytes of the kNN / features / MLP stages for n points.
 size_t knn_ws_bytes(int64_t n_ref, int64_t n_qry);
 size_t mlp_ws_bytes(int64_t B);

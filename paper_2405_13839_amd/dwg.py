@@ -31,7 +31,8 @@ class DwgError(RuntimeError):
 
 class KernelParams(ctypes.Structure):
     _fields_ = [("lam", ctypes.c_float), ("eps", ctypes.c_float), ("compensated", ctypes.c_int),
-                ("split", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
+                ("split", ctypes.c_int), ("tree_beta", ctypes.c_float), ("tree_leaf", ctypes.c_int),
+                ("reserved", ctypes.c_int * 2)]
 
 
 class IterateParams(ctypes.Structure):
@@ -72,12 +73,13 @@ def load():
     lib.dwg_delta_knn_mean.argtypes = [vp, i64, i32, f32, vp, vp, sz, vp]
     lib.dwg_delta_anchor_mean.argtypes = [vp, i64, i32, i64, f32, vp, vp, sz, vp]
     lib.dwg_mlp_param_count.restype = i64
+    lib.dwg_octree.argtypes = [vp, i64, i32, vp, vp, i64, ctypes.POINTER(i64), vp, sz, vp]
     lib.dwg_features.argtypes = [vp, i64, i64, vp, vp, sz, vp]
     lib.dwg_mlp_infer.argtypes = [vp, vp, i64, vp, vp, sz, vp]
     lib.dwg_mlp_train_step.argtypes = [vp, vp, vp, i64, f32, vp, vp, vp, i64, vp, vp, vp, sz, vp]
     for name in ["dwg_gwn_eval", "dwg_gwn_grad", "dwg_iterate", "dwg_init_normals", "dwg_knn",
                  "dwg_delta_knn_mean", "dwg_delta_anchor_mean", "dwg_features", "dwg_mlp_infer",
-                 "dwg_mlp_train_step"]:
+                 "dwg_mlp_train_step", "dwg_octree"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -86,7 +88,7 @@ def load():
 EXPORTED = ["dwg_version", "dwg_status_string", "dwg_last_error", "dwg_workspace_bytes", "dwg_gwn_eval",
             "dwg_gwn_grad", "dwg_iterate", "dwg_init_normals", "dwg_knn", "dwg_delta_knn_mean",
             "dwg_delta_anchor_mean", "dwg_mlp_param_count", "dwg_features", "dwg_mlp_infer",
-            "dwg_mlp_train_step"]
+            "dwg_mlp_train_step", "dwg_octree"]
 
 
 def version() -> str:
@@ -128,10 +130,12 @@ class Params:
     eps: float = 0.0
     compensated: bool = True
     split: int = 0
+    beta: float = 0.0  # 0 = exact all-pairs sum; >= 1 = octree traversal (paper: 2.3)
+    leaf: int = 0      # octree leaf capacity (0 = 16)
 
     def c(self):
         return KernelParams(float(self.lam), float(self.eps), int(bool(self.compensated)), int(self.split),
-                            (ctypes.c_int * 4)(0, 0, 0, 0))
+                            float(self.beta), int(self.leaf), (ctypes.c_int * 2)(0, 0))
 
 
 def workspace_bytes(n_src: int, n_qry: int, params: Params | None = None) -> int:
@@ -204,6 +208,23 @@ def random_normals(n: int, seed: int, device) -> torch.Tensor:
     _check(lib.dwg_init_normals(INIT_RANDOM, ctypes.c_uint64(seed), None, n, None, _ptr(N), None, 0,
                                 _stream(N.device)))
     return N
+
+
+def octree(P, leaf: int = 0, ws=None):
+    """Octree of the octree mode: (perm int32 [n], nodes int32 [count, 4] = (start, end,
+    level, skip) in depth-first pre-order), both on P's device."""
+    lib = load()
+    P = _dev(P, "P")
+    n = P.shape[1]
+    if ws is None:
+        ws = workspace(n, n, P.device, Params(beta=2.3, leaf=leaf))
+    perm = torch.empty(n, dtype=torch.int32, device=P.device)
+    cap = 2 * n
+    nodes = torch.empty((cap, 4), dtype=torch.int32, device=P.device)
+    cnt = ctypes.c_int64(0)
+    _check(lib.dwg_octree(_ptr(P), n, int(leaf), _ptr(perm), _ptr(nodes), cap, ctypes.byref(cnt), _ptr(ws),
+                          ws.numel(), _stream(P.device)))
+    return perm, nodes[:cnt.value]
 
 
 def pca_normals(P, ws=None) -> torch.Tensor:

@@ -1,0 +1,141 @@
+"""Octree mode (Sec. 5.2 "Octree Traversal") through the C ABI against the octree oracle:
+the tree itself bit-exact (dwg_octree: Morton order and pre-order nodes), w and grad w to the
+GWN tolerance at sizes that span many nodes and leaves, one full iteration, and sampled
+queries at 1M points. Every input comes from the seeded generators or the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_13839_amd import synth
+from tests.helpers import TOL_G, TOL_W, cuda, e_g, e_w, host, unit_rows
+
+pytestmark = pytest.mark.gpu
+
+
+def _dwg():
+    from paper_2405_13839_amd import dwg
+    return dwg
+
+
+def _clusters(n, seed):
+    rng = np.random.default_rng(seed)
+    P = np.concatenate([rng.normal(0, 1e-4, (3, n // 2)), 1 + rng.normal(0, 1e-5, (3, n - n // 2))], axis=1)
+    P[:, 5] = P[:, 6]
+    P[:, 7] = P[:, 6]
+    return P.astype(np.float32)
+
+
+CLOUDS = {
+    "single": lambda: np.array([[0.5], [0.25], [1.0]], np.float32),
+    "uniform_17": lambda: np.random.default_rng(1).uniform(-1, 1, (3, 17)).astype(np.float32),
+    "uniform_5000": lambda: np.random.default_rng(2).uniform(-1, 1, (3, 5000)).astype(np.float32),
+    "clusters_dups_4000": lambda: _clusters(4000, 3),
+    "all_equal_100": lambda: np.zeros((3, 100), np.float32),
+    "torus_ellipsoids_100K": lambda: synth.torus_ellipsoids(100_000, seed=501).P,
+}
+
+
+@pytest.mark.parametrize("leaf", [1, 4, 16])
+@pytest.mark.parametrize("cloud", list(CLOUDS))
+def test_octree_matches_oracle(cloud, leaf):
+    dwg = _dwg()
+    P = CLOUDS[cloud]()
+    perm, nodes = dwg.octree(cuda(P), leaf)
+    operm, oinfo = oracle.octree(P, leaf)
+    np.testing.assert_array_equal(host(perm).astype(np.int64), operm)
+    np.testing.assert_array_equal(host(nodes).astype(np.int64), oinfo)
+
+
+CASES = [
+    # generator, lambda, use delta, compensated, beta, leaf, queries (None = the sources)
+    ("sphere_3000", 0.0, False, True, 2.3, 16, None),
+    ("sphere_3000", 10.0, True, False, 2.3, 4, None),
+    ("torus_ellipsoids_20000", 10.0, True, True, 2.3, 16, None),
+    ("torus_ellipsoids_20000", 0.0, True, True, 4.0, 16, None),
+    ("torus_ellipsoids_20000", 10.0, True, True, 2.3, 1, 3001),
+    ("superquadrics_plates_30000", 0.0, True, True, 2.3, 32, None),
+]
+
+
+def _gen(name):
+    kind, n = name.rsplit("_", 1)
+    n = int(n)
+    if kind == "sphere":
+        return synth.sphere(n, 0.005, 100)
+    return getattr(synth, kind)(n, seed=777)
+
+
+@pytest.mark.parametrize("gen,lam,use_delta,comp,beta,leaf,nq", CASES)
+def test_tree_gwn_matches_oracle(gen, lam, use_delta, comp, beta, leaf, nq):
+    dwg = _dwg()
+    c = _gen(gen)
+    rng = np.random.default_rng(11)
+    N = unit_rows(rng, c.n)
+    d = oracle.anchor_delta(c.P).astype(np.float32) if use_delta else None
+    Q = c.P if nq is None else rng.uniform(c.P.min(axis=1, keepdims=True), c.P.max(axis=1, keepdims=True),
+                                           (3, nq)).astype(np.float32)
+    prm = dwg.Params(lam=lam, compensated=comp, beta=beta, leaf=leaf)
+    Pc = cuda(c.P)
+    w, g = dwg.gwn(Pc, cuda(N), cuda(c.area), None if d is None else cuda(d), Pc if nq is None else cuda(Q), prm)
+    w_ref, g_ref, flag = oracle.tree_gwn(c.P, N, c.area, d, Q, lam=lam, beta=beta, leaf=leaf)
+    ok = flag == 0
+    assert ok.mean() > 0.99
+    ew, eg = e_w(host(w)[ok], w_ref[ok]), e_g(host(g)[:, ok], g_ref[:, ok])
+    print(f"[tree] {gen} lam={lam} beta={beta} leaf={leaf}: e_w={ew:.2e} e_g={eg:.2e} flagged={int((~ok).sum())}")
+    assert ew <= TOL_W and eg <= TOL_G
+
+
+def test_tree_huge_beta_is_the_all_pairs_sum():
+    """beta = 1e30 opens every node: the octree kernel then sums every source one by one."""
+    dwg = _dwg()
+    c = synth.torus_ellipsoids(8000, seed=778)
+    rng = np.random.default_rng(12)
+    N = unit_rows(rng, c.n)
+    d = oracle.anchor_delta(c.P).astype(np.float32)
+    Pc = cuda(c.P)
+    w, g = dwg.gwn(Pc, cuda(N), cuda(c.area), cuda(d), Pc, dwg.Params(lam=10.0, beta=1e30))
+    w_ref, g_ref, flag = oracle.gwn(c.P, N, c.area, d, c.P, lam=10.0)
+    assert e_w(host(w), w_ref) <= TOL_W and e_g(host(g), g_ref, skip=flag) <= TOL_G
+
+
+def test_tree_iteration_matches_oracle():
+    """One dwg_iterate step in octree mode: n_new = -grad / |grad| of the oracle's octree
+    gradient on the same inputs, and the same mean w."""
+    dwg = _dwg()
+    c = synth.torus_ellipsoids(20_000, seed=779)
+    N0 = oracle.random_normals(5, c.n).astype(np.float32)
+    d = oracle.anchor_delta(c.P).astype(np.float32)
+    Nt = cuda(N0)
+    st, stats = dwg.iterate(cuda(c.P), cuda(c.area), cuda(d), Nt, dwg.Params(lam=10.0, beta=2.3), max_iters=1,
+                            fixed_iters=True)
+    w_ref, g_ref, flag = oracle.tree_gwn(c.P, N0, c.area, d, c.P, lam=10.0, beta=2.3)
+    N1, _ = oracle.update(g_ref, N0)
+    from tests.helpers import angle_deg
+    ang = angle_deg(host(Nt), N1)
+    ok = flag == 0
+    assert np.percentile(ang[ok], 99.9) <= 1e-2 and np.mean(ang[ok] <= 1e-3) > 0.99
+    assert abs(stats[0, 0] - w_ref.mean()) <= 1e-5 * max(1.0, abs(w_ref.mean()))
+
+
+def test_tree_full_size_sampled_1M():
+    """1M points (torus + 2 ellipsoids, screened): all queries on the GPU in octree mode,
+    300 sampled queries recomputed by the octree oracle over all sources; the octree error
+    against the exact sum is printed."""
+    dwg = _dwg()
+    c = synth.torus_ellipsoids(1_000_000, seed=102)
+    rng = np.random.default_rng(17)
+    N = unit_rows(rng, c.n)
+    from tests.test_gpu_configs import anchor_radius
+    d = anchor_radius(c.P)
+    Pc = cuda(c.P)
+    w, g = dwg.gwn(Pc, cuda(N), cuda(c.area), cuda(d), Pc, dwg.Params(lam=10.0, beta=2.3))
+    sel = np.sort(rng.choice(c.n, 300, replace=False))
+    Q = np.ascontiguousarray(c.P[:, sel])
+    w_ref, g_ref, flag = oracle.tree_gwn(c.P, N, c.area, d, Q, lam=10.0, beta=2.3)
+    ok = flag == 0
+    wg, gg = host(w)[sel], host(g)[:, sel]
+    ew, eg = e_w(wg[ok], w_ref[ok]), e_g(gg[:, ok], g_ref[:, ok])
+    w_ex, g_ex, _ = oracle.gwn(c.P, N, c.area, d, Q[:, :50], lam=10.0)
+    print(f"[tree] 1M: e_w={ew:.2e} e_g={eg:.2e} flagged={int((~ok).sum())}; octree vs exact on 50 queries: "
+          f"e_w={e_w(wg[:50], w_ex):.2e} e_g={e_g(gg[:, :50], g_ex):.2e}")
+    assert ew <= TOL_W and eg <= TOL_G

@@ -35,32 +35,48 @@ def test_tree_opening_everything_is_exact(lam, leaf):
 
 
 def _geometric_octree(P, leaf, depth=21):
-    """Nodes as (level, sorted point indices) by explicit recursive subdivision of the cube."""
+    """Nodes as (level, sorted point indices) by explicit recursive subdivision of the cube
+    (a cell with a single non-empty child is represented by that child)."""
     P = np.asarray(P, np.float64)
     lo = P.min(axis=1)
     ext = (P.max(axis=1) - lo).max()
     out = []
 
-    def rec(idx, level, cell):
-        out.append((level, tuple(sorted(idx))))
-        if len(idx) <= leaf or level == depth:
-            return
+    def children(idx, level):
         h = ext / 2 ** (level + 1)
         kids = {}
         for i in idx:
             c = tuple(int(min(max(math.floor((P[d, i] - lo[d]) / h), 0), 2 ** (level + 1) - 1)) for d in range(3))
             kids.setdefault(c, []).append(i)
-        for c in sorted(kids, key=lambda c: [((c[0] >> b) & 1, (c[1] >> b) & 1, (c[2] >> b) & 1)
-                                            for b in range(level, -1, -1)]):
-            rec(kids[c], level + 1, c)
+        return [kids[c] for c in sorted(kids, key=lambda c: [((c[0] >> b) & 1, (c[1] >> b) & 1, (c[2] >> b) & 1)
+                                                              for b in range(level, -1, -1)])]
 
-    rec(list(range(P.shape[1])), 0, (0, 0, 0))
+    def rec(idx, level):
+        if len(idx) <= leaf or level == depth:
+            out.append((level, tuple(sorted(idx))))
+            return
+        kids = children(idx, level)
+        if len(kids) == 1:  # same point set as its only child: one node, at the deeper cell
+            rec(kids[0], level + 1)
+            return
+        out.append((level, tuple(sorted(idx))))
+        for k in kids:
+            rec(k, level + 1)
+
+    rec(list(range(P.shape[1])), 0)
     return out
 
 
-@pytest.mark.parametrize("n,leaf", [(1, 1), (7, 1), (300, 4), (2000, 16)])
+@pytest.mark.parametrize("n,leaf", [(1, 1), (7, 1), (300, 4), (2000, 16), (-400, 4)])
 def test_octree_matches_geometric_subdivision(n, leaf):
-    P = _cloud(n, 3 + n)[0]
+    if n > 0:
+        P = _cloud(n, 3 + n)[0]
+    else:  # two tight clusters far apart: long single-child chains, and duplicate points
+        n = -n
+        rng = np.random.default_rng(9)
+        P = np.concatenate([rng.normal(0, 1e-4, (3, n // 2)), 1 + rng.normal(0, 1e-5, (3, n // 2))], axis=1)
+        P[:, 5] = P[:, 6]
+        P = P.astype(np.float32)
     perm, info = oracle.octree(P, leaf)
     ref = _geometric_octree(P, leaf)
     assert len(info) == len(ref)
@@ -68,11 +84,13 @@ def test_octree_matches_geometric_subdivision(n, leaf):
         assert lev == rl and tuple(sorted(perm[s:e])) == ri
     # pre-order: skip is the index just past the subtree; children tile the parent's range
     assert sorted(perm.tolist()) == list(range(n))
+    assert len(info) <= 2 * n
     for k, (s, e, lev, skip) in enumerate(info):
         assert skip > k and (skip == len(info) or info[skip][0] >= e)
+        assert skip == k + 1 or info[k + 1][1] < e  # an internal node has >= 2 children
         c, pos = k + 1, s
         while c < skip:
-            assert info[c][2] == lev + 1 and info[c][0] == pos
+            assert info[c][2] > lev and info[c][0] == pos
             pos = info[c][1]
             c = info[c][3]
         assert skip == k + 1 or pos == e
