@@ -11,6 +11,8 @@ One step = one complete orientation solve with the inputs resident in HBM: kNN r
 initial normals (learned MLP init when its weights exist, else random), then DWG
 iterations (all-pairs screened GWN + gradient, normal update, FP64 iso-value and top-1%
 convergence statistic) until the convergence test passes or --max-iters.
+After the timed steps, one solve with the octree evaluation (Sec. 5.2, opening factor
+--tree-beta) is timed on its own and reported under "octree".
 
 value = pair interactions evaluated / second over the timed steps (whole job).
 Prints one JSON line (rank 0, N = 1 GPU only).
@@ -29,11 +31,15 @@ FLOP_PER_PAIR = {False: 32, True: 44}  # algorithmic FLOP per (query, source) pa
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (256 CU x 2.4 GHz x 256 FLOP/clk)
 WEIGHTS = os.path.join(ROOT, "paper_2405_13839_amd", "weights", "mlp_init.safetensors")
 TRAFFIC = os.path.join(ROOT, "profiles", "gwn_traffic.json")
-GWN_SRC = os.path.join(ROOT, "paper_2405_13839_amd", "csrc", "dwg_gwn.hip")
+GWN_SRC = [os.path.join(ROOT, "paper_2405_13839_amd", "csrc", f) for f in ("dwg_gwn.hip", "dwg_pair.h")]
 
 
 def kernel_sha() -> str:
-    return hashlib.sha256(open(GWN_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the all-pairs kernel's sources (its file and the shared pair arithmetic)."""
+    h = hashlib.sha256()
+    for f in GWN_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def traffic_per_launch(n: int):
@@ -62,6 +68,8 @@ def main() -> int:
     ap.add_argument("--cpu-queries", type=int, default=4096,
                     help="queries of the oracle CPU-baseline sample (0 = skip)")
     ap.add_argument("--seed", type=int, default=102)
+    ap.add_argument("--tree-beta", type=float, default=2.3,
+                    help="opening factor of the one extra octree-mode solve (Sec. 5.2 traversal; 0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding of the "
@@ -89,13 +97,13 @@ def main() -> int:
         from paper_2405_13839_amd import mlp_init
         mlp = mlp_init.load_params(WEIGHTS, dev)
 
-    def solve(kind, max_iters, seed=202):
-        delta = dwg.delta_anchor_mean(P, 10, 4096, 1.0, ws=ws)
+    def solve(kind, max_iters, seed=202, params=prm, wsp=ws):
+        delta = dwg.delta_anchor_mean(P, 10, 4096, 1.0, ws=wsp)
         if kind == "mlp":
-            N = dwg.mlp_normals(P, mlp, ws=ws)
+            N = dwg.mlp_normals(P, mlp, ws=wsp)
         else:
             N = dwg.random_normals(n, seed, dev)
-        st, stats = dwg.iterate(P, area, delta, N, prm, max_iters=max_iters, eps_deg=0.1, ws=ws)
+        st, stats = dwg.iterate(P, area, delta, N, params, max_iters=max_iters, eps_deg=0.1, ws=wsp)
         return N, st, stats
 
     for _ in range(args.warmup):
@@ -165,6 +173,28 @@ def main() -> int:
         rr = metrics.orientation_report(Nr.cpu().numpy(), cloud.N_true, cloud.comp)
         result["random_init"] = {"seconds": time.perf_counter() - t1, "iterations": int(sr.shape[0]),
                                  "converged": int(str_) == dwg.DWG_OK, "orientation": rr}
+
+    if args.tree_beta > 0:
+        # the same solve with the octree evaluation of Sec. 5.2 (approximate field), timed alone
+        tprm = dwg.Params(lam=args.lam, beta=args.tree_beta)
+        del ws
+        torch.cuda.empty_cache()
+        wst = dwg.workspace(n, n, dev, tprm)
+        solve(init, args.max_iters, params=tprm, wsp=wst)  # warm-up
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        Nt, stt, stt_stats = solve(init, args.max_iters, params=tprm, wsp=wst)
+        torch.cuda.synchronize()
+        tt = time.perf_counter() - t3
+        rt = metrics.orientation_report(Nt.cpu().numpy(), cloud.N_true, cloud.comp)
+        result["octree"] = {
+            "beta": args.tree_beta,
+            "time_to_converged_s": tt,
+            "iterations": int(stt_stats.shape[0]),
+            "converged": int(stt) == dwg.DWG_OK,
+            "eval_ms_per_iteration": float(stt_stats[:, 3].mean()),
+            "orientation": rt,
+        }
 
     if args.cpu_queries > 0:
         import oracle

@@ -50,7 +50,7 @@ typedef struct dwg_kernel_params {
   int split;       /* all-pairs source splits: 0 = automatic, else 1..64 */
   float tree_beta; /* 0 = exact all-pairs sum; >= 1 = octree traversal (Sec. 5.2) with
                       opening radius max(tree_beta * r, r + dmax) per node (paper: 2.3) */
-  int tree_leaf;   /* octree leaf capacity: 0 = 16, else 1..1024 */
+  int tree_leaf;   /* octree leaf capacity: 0 = 32, else 1..1024 */
   int reserved[2]; /* must be zero */
 } dwg_kernel_params;
 
@@ -133,7 +133,7 @@ dwg_status dwg_gwn_grad(const float* P, const float* N, const float* area, const
 
 /*
  * dwg_octree -- the octree of the octree mode for P [3][n] with leaf capacity `leaf`
- * (0 = 16). Synchronous. Outputs: perm [n] int32 (i-th source in Morton order); nodes
+ * (0 = 32). Synchronous. Outputs: perm [n] int32 (i-th source in Morton order); nodes
  * [cap][4] int32 = (start, end, level, skip) per node in depth-first pre-order, where
  * [start, end) is the node's range of sorted positions and skip the index of the first node
  * after its subtree; *count (HOST) = number of nodes, at most 2n - 1 (cap >= 2n always

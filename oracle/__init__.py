@@ -247,7 +247,7 @@ def gauss_normals(P):
 TREE_DEPTH = 21
 
 
-def octree(P, leaf=16):
+def octree(P, leaf=32):
     """Octree of Sec. 5.2 as built by tree_oracle.c: (perm int64 [n], info int64 [nodes, 4] =
     (start, end, level, skip) in depth-first pre-order)."""
     lib = _load()
@@ -265,7 +265,7 @@ def octree(P, leaf=16):
         cap = int(cnt)
 
 
-def tree_gwn(P, N, area, delta, Q, lam=0.0, eps=0.0, beta=2.3, leaf=16, grad=True, visits=False):
+def tree_gwn(P, N, area, delta, Q, lam=0.0, eps=0.0, beta=2.3, leaf=32, grad=True, visits=False):
     """Octree-approximated w [m], grad w [3,m] (or None), flags [m] (and visited-node counts
     [m] when visits=True): Sec. 5.2 traversal with opening radius max(beta r, r + dmax)."""
     lib = _load()

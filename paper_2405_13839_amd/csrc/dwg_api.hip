@@ -40,7 +40,7 @@ namespace {
   } while (0)
 
 const dwg_kernel_params kDefaultKp = {0.0f, 0.0f, 1, 0, 0.0f, 0, {0, 0}};
-constexpr int kDefaultLeaf = 16;
+constexpr int kDefaultLeaf = 32;
 
 bool tree_mode(const dwg_kernel_params& kp) { return kp.tree_beta > 0.0f; }
 int tree_leaf(const dwg_kernel_params& kp) { return kp.tree_leaf > 0 ? kp.tree_leaf : kDefaultLeaf; }

@@ -491,6 +491,9 @@ __device__ __forceinline__ void fold(float* sum, float* cmp, const float* acc) {
 }
 
 // Traversal: one thread per sorted query, one node index per wavefront (see the file head).
+// Contributions are summed in FP32 into `acc` and folded into the (Kahan-compensated when
+// KAHAN) running sums after every leaf visit and at the end. The next node is usually i + 1
+// (a node opened, or a leaf, whose skip is i + 1), so its data is loaded one step ahead.
 template <bool GRAD, bool SCREENED, bool KAHAN>
 __global__ __launch_bounds__(256) void k_tree_eval(const float* __restrict__ Q, int64_t m,
                                                    const int32_t* __restrict__ qperm, const int4* __restrict__ node,
@@ -503,31 +506,31 @@ __global__ __launch_bounds__(256) void k_tree_eval(const float* __restrict__ Q, 
   const int64_t o = qperm[qi < m ? qi : m - 1];
   const float qx = Q[o], qy = Q[m + o], qz = Q[2 * m + o];
   const double dqx = qx, dqy = qy, dqz = qz;
-  float sum[NA], cmp[NA];
+  float sum[NA], cmp[NA], acc[NA];
 #pragma unroll
-  for (int a = 0; a < NA; ++a) sum[a] = cmp[a] = 0.0f;
+  for (int a = 0; a < NA; ++a) sum[a] = cmp[a] = acc[a] = 0.0f;
   int nn = __builtin_amdgcn_readfirstlane(*total_p);
   if (nn > cap) nn = (int)cap;
   int skip_to = 0;
   int i = 0;
+  int4 nd = node[0];
+  double4 g = geo[0];
+  float4 mm = mom[0];
   while (i < nn) {
-    const int4 nd = node[i];
+    const int nxt = i + 1 < nn ? i + 1 : i;
+    const int4 nd1 = node[nxt];
+    const double4 g1 = geo[nxt];
+    const float4 mm1 = mom[nxt];
     const int nskip = __builtin_amdgcn_readfirstlane(nd.z);
     bool open = false, direct = false;
     if (i >= skip_to) {
-      const double4 g = geo[i];
       const double dx = g.x - dqx, dy = g.y - dqy, dz = g.z - dqz;
       const double d2 = dx * dx + dy * dy + dz * dz;
       if (d2 > g.w) {
-        const float4 mm = mom[i];
-        float acc[NA];
-#pragma unroll
-        for (int a = 0; a < NA; ++a) acc[a] = 0.0f;
         if (SCREENED)
           pair_screened_d<GRAD, true>((float)dx, (float)dy, (float)dz, 0.0f, mm, sk, acc);
         else
           pair_plain_d<GRAD, true>((float)dx, (float)dy, (float)dz, 0.0f, mm, acc);
-        fold<NA, KAHAN>(sum, cmp, acc);
         skip_to = nskip;
       } else if (nd.w >> 8) {
         direct = true;
@@ -535,30 +538,42 @@ __global__ __launch_bounds__(256) void k_tree_eval(const float* __restrict__ Q, 
         open = true;
       }
     }
+    int next;
     if (__any(open)) {
-      ++i;
-      continue;
-    }
-    if (__any(direct)) {
-      const int s0 = __builtin_amdgcn_readfirstlane(nd.x);
-      int s1 = __builtin_amdgcn_readfirstlane(nd.y);
-      if (s1 > n_src) s1 = (int)n_src;
-      float acc[NA];
-#pragma unroll
-      for (int a = 0; a < NA; ++a) acc[a] = 0.0f;
-      for (int j = s0; j < s1; ++j) {
-        const float4 a = src[2 * (int64_t)j], b = src[2 * (int64_t)j + 1];
-        if (direct) {
-          if (SCREENED)
-            pair_screened<GRAD, false>(a, b, qx, qy, qz, sk, acc);
-          else
-            pair_plain<GRAD, false>(a, b, qx, qy, qz, acc);
+      next = i + 1;
+    } else {
+      if (__any(direct)) {
+        const int s0 = __builtin_amdgcn_readfirstlane(nd.x);
+        int s1 = __builtin_amdgcn_readfirstlane(nd.y);
+        if (s1 > n_src) s1 = (int)n_src;
+#pragma unroll 4
+        for (int j = s0; j < s1; ++j) {
+          const float4 a = src[2 * (int64_t)j], b = src[2 * (int64_t)j + 1];
+          if (direct) {
+            if (SCREENED)
+              pair_screened<GRAD, false>(a, b, qx, qy, qz, sk, acc);
+            else
+              pair_plain<GRAD, false>(a, b, qx, qy, qz, acc);
+          }
         }
+        fold<NA, KAHAN>(sum, cmp, acc);
+#pragma unroll
+        for (int a = 0; a < NA; ++a) acc[a] = 0.0f;
       }
-      if (direct) fold<NA, KAHAN>(sum, cmp, acc);
+      next = nskip > i ? nskip : i + 1;  // pre-order: skip > i always; guards the loop regardless
     }
-    i = nskip > i ? nskip : i + 1;  // pre-order: skip > i always; guards the loop regardless
+    if (next == i + 1) {
+      nd = nd1;
+      g = g1;
+      mm = mm1;
+    } else if (next < nn) {
+      nd = node[next];
+      g = geo[next];
+      mm = mom[next];
+    }
+    i = __builtin_amdgcn_readfirstlane(next);
   }
+  fold<NA, KAHAN>(sum, cmp, acc);
 #pragma unroll
   for (int a = 0; a < NA; ++a) part[a * mpad + qi] = KAHAN ? sum[a] - cmp[a] : sum[a];
 }

@@ -131,7 +131,7 @@ class Params:
     compensated: bool = True
     split: int = 0
     beta: float = 0.0  # 0 = exact all-pairs sum; >= 1 = octree traversal (paper: 2.3)
-    leaf: int = 0      # octree leaf capacity (0 = 16)
+    leaf: int = 0      # octree leaf capacity (0 = 32)
 
     def c(self):
         return KernelParams(float(self.lam), float(self.eps), int(bool(self.compensated)), int(self.split),
