@@ -65,7 +65,7 @@ def main() -> int:
     ap.add_argument("--max-iters", type=int, default=50)
     ap.add_argument("--compare-iters", type=int, default=20,
                     help="iteration cap of the one untimed random-init comparison solve (0 = skip)")
-    ap.add_argument("--cpu-queries", type=int, default=4096,
+    ap.add_argument("--cpu-queries", type=int, default=16384,
                     help="queries of the oracle CPU-baseline sample (0 = skip)")
     ap.add_argument("--seed", type=int, default=102)
     ap.add_argument("--tree-beta", type=float, default=2.3,
