@@ -193,6 +193,31 @@ dwg_status dwg_knn(const float* R, int64_t nr, const float* Q, int64_t m, int se
                    int32_t* idx, float* dist, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * dwg_delta_knn_window -- the paper's kernel radius (Sec. 5.2 "Poisson Kernels"): delta_i =
+ * mean of those distances from p_i to its k nearest other points that lie in [vmin, vmax]
+ * (paper: k = 10, vmin = 0.0015, vmax = 0.015 in the model's units); when none lies in the
+ * window, the mean of all k clamped to [vmin, vmax]. async. P [3][n]; delta: output [n];
+ * 1 <= k <= 16, k < n < 2^31, finite 0 <= vmin <= vmax. Workspace as dwg_workspace_bytes(n, n).
+ */
+dwg_status dwg_delta_knn_window(const float* P, int64_t n, int k, float vmin, float vmax, float* delta,
+                                void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * dwg_voronoi_area -- area weights a_i (Sec. 5.1 "Computing Area Weights"). async. For each
+ * p_i: its m nearest other points (paper: m = 15); the plane through p_i normal to the
+ * smallest-eigenvalue eigenvector of the covariance (FP64) of p_i and those points about
+ * their mean; the points projected onto the plane; a_i = area of p_i's cell in the 2D
+ * Voronoi diagram of the projections, bounded by the square [-R, R]^2 around p_i, R = the
+ * largest projected distance (so that a point with all neighbours on one side gets a finite
+ * cell), whose axes are u = n x e_k / |n x e_k| (e_k = the coordinate axis with the smallest
+ * |n_k|, the first on ties) and n x u. Coincident neighbours bound nothing; a_i = 0 when all are coincident with p_i.
+ * P [3][n]; area: output [n]; 3 <= m <= 16, m < n < 2^31. Workspace as
+ * dwg_workspace_bytes(n, n).
+ */
+dwg_status dwg_voronoi_area(const float* P, int64_t n, int m, float* area, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/*
  * dwg_delta_knn_mean -- per-point kernel radius delta_i = mean distance to the k nearest
  * other points (Sec. 5.2 "Poisson Kernels", without the absolute distance filter), times
  * `scale`. async. P [3][n]; delta: output [n]; 1 <= k <= 16, k < n; scale > 0.

@@ -285,3 +285,50 @@ def tree_gwn(P, N, area, delta, Q, lam=0.0, eps=0.0, beta=2.3, leaf=32, grad=Tru
     if rc != 0:
         raise ValueError("orc_tree_gwn rejected its arguments")
     return (w, g, fl, vis) if visits else (w, g, fl)
+
+
+def voronoi_area(P, m=15):
+    """Area weights of Sec. 5.1: per point, the m nearest other points, the tangent plane
+    through p_i normal to the smallest-eigenvalue eigenvector (numpy eigh) of their
+    covariance with p_i about the mean, and the area of p_i's cell in the 2D Voronoi diagram
+    of the projections, bounded by the square [-R, R]^2 (R = largest projected distance) on
+    the axes u = n x e_k / |n x e_k| (e_k the coordinate axis with the smallest |n_k|) and
+    n x u, computed as a half-plane intersection by qhull
+    (scipy.spatial.HalfspaceIntersection)."""
+    from scipy.spatial import ConvexHull, HalfspaceIntersection
+    P = _d(P)
+    n = P.shape[1]
+    idx, _ = knn_self(P, m)
+    out = np.zeros(n)
+    for i in range(n):
+        nb = P[:, idx[i]]
+        X = np.concatenate([P[:, i:i + 1], nb], axis=1)
+        C = np.cov(X, bias=True) * X.shape[1]
+        _, V = np.linalg.eigh(C)
+        nv = V[:, 0]
+        k = int(np.argmin(np.abs(nv)))  # the axis least aligned with the normal (first on ties)
+        u = np.cross(nv, np.eye(3)[k])
+        u /= np.linalg.norm(u)
+        B = np.stack([u, np.cross(nv, u)], axis=1)  # the square's axes; a flipped nv flips only u
+        q = B.T @ (nb - P[:, i:i + 1])  # [2, m]
+        R = np.linalg.norm(q, axis=0).max()
+        if not R > 0:
+            continue
+        c = 0.5 * np.sum(q * q, axis=0)
+        keep = c > 0
+        hs = [[q[0, j], q[1, j], -c[j]] for j in np.nonzero(keep)[0]]
+        hs += [[1.0, 0.0, -R], [-1.0, 0.0, -R], [0.0, 1.0, -R], [0.0, -1.0, -R]]
+        h = HalfspaceIntersection(np.array(hs), np.zeros(2))
+        out[i] = ConvexHull(h.intersections).volume
+    return out
+
+
+def delta_knn_window(P, k=10, vmin=0.0015, vmax=0.015):
+    """Kernel radius of Sec. 5.2: mean of the k-NN distances inside [vmin, vmax]; when none
+    is inside, the mean of all k clamped to the window."""
+    _, dist = knn_self(P, k)
+    inside = (dist >= vmin) & (dist <= vmax)
+    cnt = inside.sum(axis=1)
+    win = np.where(cnt > 0, (dist * inside).sum(axis=1) / np.maximum(cnt, 1), 0.0)
+    allm = np.clip(dist.mean(axis=1), vmin, vmax)
+    return np.where(cnt > 0, win, allm)

@@ -407,6 +407,38 @@ dwg_status dwg_delta_knn_mean(const float* P, int64_t n, int k, float scale, flo
   return delta_from_knn(dist, n, k, scale, delta, st);
 }
 
+dwg_status dwg_delta_knn_window(const float* P, int64_t n, int k, float vmin, float vmax, float* delta,
+                                void* ws, size_t ws_bytes, void* stream) {
+  DWG_CHECK(P && delta, "P and delta must not be NULL");
+  DWG_CHECK(k >= 1 && k <= kMaxK, "k must be in [1, %d]", kMaxK);
+  DWG_CHECK(n > k && n < (int64_t(1) << 31), "need k < n < 2^31");
+  DWG_CHECK(std::isfinite(vmin) && std::isfinite(vmax) && vmin >= 0.0f && vmax >= vmin,
+            "need finite 0 <= vmin <= vmax");
+  const size_t need = aux_bytes(n);
+  DWG_CHECK(ws || ws_bytes == 0, "ws is NULL but ws_bytes > 0");
+  if (!ws || ws_bytes < need) {
+    set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+    return DWG_E_WORKSPACE;
+  }
+  DWG_PROPAGATE(check_device());
+  return delta_window(P, n, k, vmin, vmax, delta, ws, static_cast<hipStream_t>(stream));
+}
+
+dwg_status dwg_voronoi_area(const float* P, int64_t n, int m, float* area, void* ws, size_t ws_bytes,
+                            void* stream) {
+  DWG_CHECK(P && area, "P and area must not be NULL");
+  DWG_CHECK(m >= 3 && m <= kMaxK, "m must be in [3, %d]", kMaxK);
+  DWG_CHECK(n > m && n < (int64_t(1) << 31), "need m < n < 2^31");
+  const size_t need = aux_bytes(n);
+  DWG_CHECK(ws || ws_bytes == 0, "ws is NULL but ws_bytes > 0");
+  if (!ws || ws_bytes < need) {
+    set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+    return DWG_E_WORKSPACE;
+  }
+  DWG_PROPAGATE(check_device());
+  return voronoi_area(P, n, m, area, ws, static_cast<hipStream_t>(stream));
+}
+
 dwg_status dwg_delta_anchor_mean(const float* P, int64_t n, int k, int64_t n_anchor, float scale,
                                  float* delta, void* ws, size_t ws_bytes, void* stream) {
   DWG_CHECK(P && delta, "P and delta must not be NULL");

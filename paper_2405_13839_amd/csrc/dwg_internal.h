@@ -205,6 +205,9 @@ dwg_status delta_from_knn(const float* dist, int64_t n, int k, float scale, floa
                           hipStream_t stream);
 dwg_status pca_normals(const float* P, int64_t n, int k, float* N, void* ws, hipStream_t stream);
 dwg_status gauss_normals(const float* P, int64_t n, float* N, hipStream_t stream);
+dwg_status voronoi_area(const float* P, int64_t n, int m, float* area, void* ws, hipStream_t stream);
+dwg_status delta_window(const float* P, int64_t n, int k, float vmin, float vmax, float* delta, void* ws,
+                        hipStream_t stream);
 dwg_status features_run(const float* P, int64_t n, int64_t n_anchor, float* feat, void* ws,
                         size_t ws_bytes, hipStream_t stream);
 dwg_status mlp_infer_run(const float* params, const float* X, int64_t B, float* Y, void* ws,

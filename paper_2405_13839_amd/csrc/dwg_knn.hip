@@ -425,6 +425,129 @@ __global__ void k_pca_normals(const float* __restrict__ P, int64_t n, const int3
   N[2 * n + i] = (float)v[2];
 }
 
+// Area weight of p_i (Sec. 5.1 "Computing Area Weights"): the plane through p_i normal to the
+// smallest-eigenvalue eigenvector of the covariance of p_i and its m nearest other points
+// (FP64), those points projected onto it, and the area of p_i's cell in the 2D Voronoi
+// diagram of the projections: the half-planes x . q_j <= |q_j|^2 / 2 clipped (Sutherland-
+// Hodgman) starting from the square [-R, R]^2, R = the largest projected distance, which
+// bounds the cell of a point whose neighbours lie on one side; the square's axes are
+// u = n x e_k / |n x e_k| (e_k the axis with the smallest |n_k|, the first on ties) and n x u. Coincident neighbours
+// (q_j = 0) bound nothing and are skipped; all-coincident neighbourhoods give 0.
+__global__ void k_voronoi_area(const float* __restrict__ P, int64_t n, const int32_t* __restrict__ idx, int m,
+                               float* __restrict__ area) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double px = P[i], py = P[n + i], pz = P[2 * n + i];
+  double mx = px, my = py, mz = pz;
+  for (int t = 0; t < m; ++t) {
+    const int64_t j = idx[i * m + t];
+    mx += P[j];
+    my += P[n + j];
+    mz += P[2 * n + j];
+  }
+  const double inv = 1.0 / (double)(m + 1);
+  mx *= inv;
+  my *= inv;
+  mz *= inv;
+  double a[6] = {0, 0, 0, 0, 0, 0};
+  for (int t = -1; t < m; ++t) {
+    const int64_t j = t < 0 ? i : (int64_t)idx[i * m + t];
+    const double x = P[j] - mx, y = P[n + j] - my, z = P[2 * n + j] - mz;
+    a[0] += x * x;
+    a[1] += x * y;
+    a[2] += x * z;
+    a[3] += y * y;
+    a[4] += y * z;
+    a[5] += z * z;
+  }
+  double nv[3];
+  smallest_eigvec(a, nv);
+  // orthonormal basis (u, w) of the plane: u = nv x (the axis least aligned with nv)
+  const double ax = fabs(nv[0]), ay = fabs(nv[1]), az = fabs(nv[2]);
+  const double e0 = (ax <= ay && ax <= az) ? 1.0 : 0.0;
+  const double e1 = (e0 == 0.0 && ay <= az) ? 1.0 : 0.0;
+  const double e2 = (e0 == 0.0 && e1 == 0.0) ? 1.0 : 0.0;
+  double u0 = nv[1] * e2 - nv[2] * e1, u1 = nv[2] * e0 - nv[0] * e2, u2 = nv[0] * e1 - nv[1] * e0;
+  const double ul = sqrt(u0 * u0 + u1 * u1 + u2 * u2);
+  u0 /= ul;
+  u1 /= ul;
+  u2 /= ul;
+  const double w0 = nv[1] * u2 - nv[2] * u1, w1 = nv[2] * u0 - nv[0] * u2, w2 = nv[0] * u1 - nv[1] * u0;
+  double qx[kMaxK], qy[kMaxK];
+  double R = 0.0;
+  for (int t = 0; t < m; ++t) {
+    const int64_t j = idx[i * m + t];
+    const double dx = P[j] - px, dy = P[n + j] - py, dz = P[2 * n + j] - pz;
+    qx[t] = dx * u0 + dy * u1 + dz * u2;
+    qy[t] = dx * w0 + dy * w1 + dz * w2;
+    const double r = sqrt(qx[t] * qx[t] + qy[t] * qy[t]);
+    R = r > R ? r : R;
+  }
+  if (!(R > 0.0)) {
+    area[i] = 0.0f;
+    return;
+  }
+  constexpr int kMaxV = kMaxK + 6;
+  double vx[2][kMaxV], vy[2][kMaxV];
+  int nvtx = 4, cur = 0;
+  vx[0][0] = -R, vy[0][0] = -R;
+  vx[0][1] = R, vy[0][1] = -R;
+  vx[0][2] = R, vy[0][2] = R;
+  vx[0][3] = -R, vy[0][3] = R;
+  for (int t = 0; t < m && nvtx > 0; ++t) {
+    const double qa = qx[t], qb = qy[t];
+    const double qc = 0.5 * (qa * qa + qb * qb);
+    if (qc == 0.0) continue;
+    const int nxt = cur ^ 1;
+    int out = 0;
+    for (int v = 0; v < nvtx; ++v) {
+      const int v2 = v + 1 == nvtx ? 0 : v + 1;
+      const double s1 = qa * vx[cur][v] + qb * vy[cur][v] - qc;
+      const double s2 = qa * vx[cur][v2] + qb * vy[cur][v2] - qc;
+      if (s1 <= 0.0 && out < kMaxV) {
+        vx[nxt][out] = vx[cur][v];
+        vy[nxt][out] = vy[cur][v];
+        ++out;
+      }
+      if (((s1 < 0.0 && s2 > 0.0) || (s1 > 0.0 && s2 < 0.0)) && out < kMaxV) {
+        const double f = s1 / (s1 - s2);
+        vx[nxt][out] = vx[cur][v] + f * (vx[cur][v2] - vx[cur][v]);
+        vy[nxt][out] = vy[cur][v] + f * (vy[cur][v2] - vy[cur][v]);
+        ++out;
+      }
+    }
+    nvtx = out;
+    cur = nxt;
+  }
+  double s = 0.0;
+  for (int v = 0; v < nvtx; ++v) {
+    const int v2 = v + 1 == nvtx ? 0 : v + 1;
+    s += vx[cur][v] * vy[cur][v2] - vx[cur][v2] * vy[cur][v];
+  }
+  area[i] = (float)(0.5 * fabs(s));
+}
+
+// Kernel radius of Sec. 5.2 "Poisson Kernels": the mean of the k nearest-neighbour distances
+// that lie in [vmin, vmax]; when none does, the mean of all k clamped to [vmin, vmax].
+__global__ void k_delta_window(const float* __restrict__ dist, int64_t n, int k, float vmin, float vmax,
+                               float* __restrict__ delta) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0, all = 0.0;
+  int c = 0;
+  for (int t = 0; t < k; ++t) {
+    const double d = dist[i * k + t];
+    all += d;
+    if (d >= vmin && d <= vmax) {
+      s += d;
+      ++c;
+    }
+  }
+  double r = c > 0 ? s / c : all / k;
+  if (c == 0) r = r < vmin ? vmin : (r > vmax ? vmax : r);
+  delta[i] = (float)r;
+}
+
 // Gauss map (Sec. 5.1 "Normal Initialization"): n_i = p_i / |p_i| (about the origin);
 // a point at the origin gets (0, 0, 1).
 __global__ void k_gauss_normals(const float* __restrict__ P, int64_t n, float* __restrict__ N) {
@@ -587,6 +710,30 @@ dwg_status pca_normals(const float* P, int64_t n, int k, float* N, void* ws, hip
   dwg_status s = knn_run(P, n, P, n, 1, nullptr, k, idx, dist, static_cast<char*>(ws) + c.used, 0, stream);
   if (s != DWG_OK) return s;
   hipLaunchKernelGGL(k_pca_normals, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, stream, P, n, idx, k, N);
+  DWG_TRY_LAUNCH();
+  return DWG_OK;
+}
+
+dwg_status voronoi_area(const float* P, int64_t n, int m, float* area, void* ws, hipStream_t stream) {
+  Carver c(ws);
+  int32_t* idx = c.take<int32_t>((size_t)n * m);
+  float* dist = c.take<float>((size_t)n * m);
+  dwg_status s = knn_run(P, n, P, n, 1, nullptr, m, idx, dist, static_cast<char*>(ws) + c.used, 0, stream);
+  if (s != DWG_OK) return s;
+  hipLaunchKernelGGL(k_voronoi_area, dim3((unsigned)cdiv(n, 128)), dim3(128), 0, stream, P, n, idx, m, area);
+  DWG_TRY_LAUNCH();
+  return DWG_OK;
+}
+
+dwg_status delta_window(const float* P, int64_t n, int k, float vmin, float vmax, float* delta, void* ws,
+                        hipStream_t stream) {
+  Carver c(ws);
+  int32_t* idx = c.take<int32_t>((size_t)n * k);
+  float* dist = c.take<float>((size_t)n * k);
+  dwg_status s = knn_run(P, n, P, n, 1, nullptr, k, idx, dist, static_cast<char*>(ws) + c.used, 0, stream);
+  if (s != DWG_OK) return s;
+  hipLaunchKernelGGL(k_delta_window, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, stream, dist, n, k, vmin, vmax,
+                     delta);
   DWG_TRY_LAUNCH();
   return DWG_OK;
 }

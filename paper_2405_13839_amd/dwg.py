@@ -74,12 +74,14 @@ def load():
     lib.dwg_delta_anchor_mean.argtypes = [vp, i64, i32, i64, f32, vp, vp, sz, vp]
     lib.dwg_mlp_param_count.restype = i64
     lib.dwg_octree.argtypes = [vp, i64, i32, vp, vp, i64, ctypes.POINTER(i64), vp, sz, vp]
+    lib.dwg_delta_knn_window.argtypes = [vp, i64, i32, f32, f32, vp, vp, sz, vp]
+    lib.dwg_voronoi_area.argtypes = [vp, i64, i32, vp, vp, sz, vp]
     lib.dwg_features.argtypes = [vp, i64, i64, vp, vp, sz, vp]
     lib.dwg_mlp_infer.argtypes = [vp, vp, i64, vp, vp, sz, vp]
     lib.dwg_mlp_train_step.argtypes = [vp, vp, vp, i64, f32, vp, vp, vp, i64, vp, vp, vp, sz, vp]
     for name in ["dwg_gwn_eval", "dwg_gwn_grad", "dwg_iterate", "dwg_init_normals", "dwg_knn",
                  "dwg_delta_knn_mean", "dwg_delta_anchor_mean", "dwg_features", "dwg_mlp_infer",
-                 "dwg_mlp_train_step", "dwg_octree"]:
+                 "dwg_mlp_train_step", "dwg_octree", "dwg_delta_knn_window", "dwg_voronoi_area"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -88,7 +90,7 @@ def load():
 EXPORTED = ["dwg_version", "dwg_status_string", "dwg_last_error", "dwg_workspace_bytes", "dwg_gwn_eval",
             "dwg_gwn_grad", "dwg_iterate", "dwg_init_normals", "dwg_knn", "dwg_delta_knn_mean",
             "dwg_delta_anchor_mean", "dwg_mlp_param_count", "dwg_features", "dwg_mlp_infer",
-            "dwg_mlp_train_step", "dwg_octree"]
+            "dwg_mlp_train_step", "dwg_octree", "dwg_delta_knn_window", "dwg_voronoi_area"]
 
 
 def version() -> str:
@@ -208,6 +210,31 @@ def random_normals(n: int, seed: int, device) -> torch.Tensor:
     _check(lib.dwg_init_normals(INIT_RANDOM, ctypes.c_uint64(seed), None, n, None, _ptr(N), None, 0,
                                 _stream(N.device)))
     return N
+
+
+def voronoi_area(P, m: int = 15, ws=None) -> torch.Tensor:
+    """Tangent-plane Voronoi area weights [n] (Sec. 5.1)."""
+    lib = load()
+    P = _dev(P, "P")
+    n = P.shape[1]
+    if ws is None:
+        ws = workspace(n, n, P.device)
+    out = torch.empty(n, dtype=torch.float32, device=P.device)
+    _check(lib.dwg_voronoi_area(_ptr(P), n, int(m), _ptr(out), _ptr(ws), ws.numel(), _stream(P.device)))
+    return out
+
+
+def delta_knn_window(P, k: int = 10, vmin: float = 0.0015, vmax: float = 0.015, ws=None) -> torch.Tensor:
+    """The paper's windowed k-NN kernel radius [n] (Sec. 5.2)."""
+    lib = load()
+    P = _dev(P, "P")
+    n = P.shape[1]
+    if ws is None:
+        ws = workspace(n, n, P.device)
+    out = torch.empty(n, dtype=torch.float32, device=P.device)
+    _check(lib.dwg_delta_knn_window(_ptr(P), n, int(k), ctypes.c_float(vmin), ctypes.c_float(vmax), _ptr(out),
+                                    _ptr(ws), ws.numel(), _stream(P.device)))
+    return out
 
 
 def octree(P, leaf: int = 0, ws=None):
