@@ -144,6 +144,53 @@ dwg_status dwg_gwn_grad(const float* P, const float* N, const float* area, const
 dwg_status dwg_octree(const float* P, int64_t n, int leaf, int32_t* perm, int32_t* nodes, int64_t cap,
                       int64_t* count, void* ws, size_t ws_bytes, void* stream);
 
+/* Grid of the level-set update (Sec. 4.3, Algorithm 1). */
+typedef struct dwg_mc_params {
+  int depth;    /* cells per axis = 2^depth over the octree frame, 1..16 (paper: 8-13) */
+  int dilate;   /* rings of neighbour cells around the cells holding points, 0..2 */
+  int k;        /* nearest input points per face, 1..16 (paper: 10) */
+  int iso;      /* w_bar: 0 = mean of w over the input points, 1 = over the grid corners */
+} dwg_mc_params;
+
+/*
+ * Level-set update (Sec. 4.3 Eq. 6-7, Algorithm 1). The grid: the octree frame (lo =
+ * bounding-box minimum, side = largest extent) cut into 2^depth cells per axis; the
+ * evaluated cells are those holding points plus `dilate` rings of neighbours; their
+ * corners sit at lo + c * side / 2^depth. One iteration: w at every corner (all-pairs, or
+ * octree mode when kp->tree_beta > 0) with the current normals; w_bar = the FP64 mean of w
+ * over the input points (iso = 0; evaluated in the same launch) or over the corners
+ * (iso = 1, Eq. 6 over the grid nodes); the w_bar level set by marching tetrahedra (each cube cut into 6 tetrahedra
+ * around its (0,0,0)-(1,1,1) diagonal, a corner inside when w > w_bar); per face the cross
+ * product of its edges turned away from the inside corners; each face's vector added to
+ * its k nearest input points; n_i = normalize(sum), a point with no face (or a zero sum)
+ * keeps its normal. The per-face sums use 64-bit fixed-point atomics, so results are
+ * deterministic.
+ *
+ * Workspace: dwg_mc_workspace_bytes(n, kp, mcp, cells) with the cell count `cells` from
+ * dwg_mc_cells (cells = 0 gives the bytes dwg_mc_cells itself needs).
+ */
+size_t dwg_mc_workspace_bytes(int64_t n, const dwg_kernel_params* kp, const dwg_mc_params* mcp, int64_t cells);
+/* Number of evaluated grid cells for P [3][n] (synchronous; *cells is HOST). */
+dwg_status dwg_mc_cells(const float* P, int64_t n, const dwg_mc_params* mcp, int64_t* cells, void* ws,
+                        size_t ws_bytes, void* stream);
+/*
+ * dwg_iterate_mc -- Algorithm 1 with the level-set update above; arguments, statistics and
+ * return codes as dwg_iterate (wmean = w_bar, gwn_ms = the evaluation of w). Synchronous. Needs k < n < 2^31 / (2 dilate + 1)^3.
+ */
+dwg_status dwg_iterate_mc(const float* P, const float* area, const float* delta, int64_t n, float* N_inout,
+                          const dwg_kernel_params* kp, const dwg_iterate_params* ip, const dwg_mc_params* mcp,
+                          dwg_iter_stat* stats_host, int* iters_done, void* ws, size_t ws_bytes, void* stream);
+/*
+ * dwg_level_set -- the w_bar level set of the field of (P, N) on the grid above: triangles
+ * [cap][9] float (three vertices q0, q1, q2 each, wound so that (q1 - q0) x (q2 - q0) points
+ * away from w > w_bar, i.e. outwards for outward normals), *ntri (HOST) = the number of triangles (written even when it
+ * exceeds cap; then only cap are stored and DWG_E_INVALID is returned), *iso (HOST) = w_bar.
+ * Synchronous.
+ */
+dwg_status dwg_level_set(const float* P, const float* N, const float* area, const float* delta, int64_t n,
+                         const dwg_kernel_params* kp, const dwg_mc_params* mcp, float* tri, int64_t cap,
+                         int64_t* ntri, double* iso, void* ws, size_t ws_bytes, void* stream);
+
 /*
  * dwg_iterate -- Algorithm 1 with every input point as a query (Sec. 4.3). Synchronous.
  *   Iteration t: evaluate w and grad w at every p_i with the normals n^(t-1) (self pair

@@ -19,7 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdwg.so")
-SOURCES = ["dwg_gwn.hip", "dwg_tree.hip", "dwg_sort.hip", "dwg_knn.hip", "dwg_mlp.hip", "dwg_api.hip"]
+SOURCES = ["dwg_gwn.hip", "dwg_tree.hip", "dwg_mc.hip", "dwg_sort.hip", "dwg_knn.hip", "dwg_mlp.hip",
+           "dwg_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -44,7 +45,7 @@ def _compile(src: str) -> str:
 def build(verbose: bool = True) -> str:
     """Compile every HIP source and link libdwg.so (always rebuilds)."""
     os.makedirs(OUT_DIR, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(7, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]

@@ -283,6 +283,197 @@ dwg_status dwg_iterate(const float* P, const float* area, const float* delta, in
   return result;
 }
 
+}  // extern "C"
+
+namespace {
+
+dwg_status check_mcp(const dwg_mc_params* mcp, int64_t n, McParams* out) {
+  DWG_CHECK(mcp, "mcp must not be NULL");
+  DWG_CHECK(mcp->depth >= 1 && mcp->depth <= 16, "depth must be in [1, 16]");
+  DWG_CHECK(mcp->dilate >= 0 && mcp->dilate <= 2, "dilate must be in [0, 2]");
+  DWG_CHECK(mcp->k >= 1 && mcp->k <= kMaxK, "k must be in [1, %d]", kMaxK);
+  DWG_CHECK(mcp->iso == 0 || mcp->iso == 1, "iso must be 0 (points) or 1 (grid corners)");
+  const int64_t w = 2 * mcp->dilate + 1;
+  DWG_CHECK(n > mcp->k && n * w * w * w < (int64_t(1) << 31), "need k < n < 2^31 / (2 dilate + 1)^3");
+  *out = McParams{mcp->depth, mcp->dilate, mcp->k, mcp->iso == 0 ? 1 : 0};
+  return DWG_OK;
+}
+
+size_t mc_bytes(int64_t n, const dwg_kernel_params& kp, const McParams& mp, int64_t cells) {
+  Carver c(nullptr);
+  carve_mc_grid(c, n, mp, nullptr);
+  if (cells > 0) {
+    carve_mc_faces(c, n, cells, mp.k, nullptr);
+    c.used = align256(c.used + gwn_bytes(n, 8 * cells + (mp.iso_points ? n : 0), kp));
+  }
+  return c.used;
+}
+
+// Grid, corners and the evaluation state of the level-set update; checks the workspace
+// against the actual cell count.
+dwg_status mc_prepare(const float* P, const float* N, const float* area, const float* delta, int64_t n,
+                      const dwg_kernel_params& kp, const McParams& mp, void* ws, size_t ws_bytes, hipStream_t st,
+                      McWork* w, EvalState* es) {
+  Carver c(ws);
+  carve_mc_grid(c, n, mp, w);
+  int64_t C = 0;
+  DWG_PROPAGATE(mc_cells(P, n, mp, *w, &C, st));
+  const size_t need = mc_bytes(n, kp, mp, C);
+  if (ws_bytes < need) {
+    set_error("workspace too small for %lld grid cells: %zu bytes given, %zu needed", (long long)C, ws_bytes, need);
+    return DWG_E_WORKSPACE;
+  }
+  DWG_CHECK(12 * C < (int64_t(1) << 31), "too many grid cells (%lld)", (long long)C);
+  carve_mc_faces(c, n, C, mp.k, w);
+  int64_t m = 0;
+  DWG_PROPAGATE(mc_corners(mp, *w, &m, st));
+  if (mp.iso_points) DWG_PROPAGATE(mc_append_points(P, n, *w, st));
+  DWG_PROPAGATE(knn_grid(P, n, w->knn, st));
+  DWG_PROPAGATE(mc_clear(*w, st));
+  return eval_prepare(P, N, area, delta, n, w->pos, w->ld, kp, false, static_cast<char*>(ws) + c.used, st, es);
+}
+
+// w at the corners (and at the points when w_bar is taken over them) and w_bar.
+dwg_status mc_field(const dwg_kernel_params& kp, const McParams& mp, const McWork& w, const EvalState& es,
+                    hipStream_t st) {
+  DWG_PROPAGATE(eval_run(w.pos, w.ld, kp, false, es, st));
+  if (!mp.iso_points) return launch_combine(w.ld, kp, false, w.wc, nullptr, w.iso, es.wk, st);
+  DWG_PROPAGATE(launch_combine(w.ld, kp, false, w.wc, nullptr, nullptr, es.wk, st));
+  return mc_point_iso(w, w.wc + w.m, w.n, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t dwg_mc_workspace_bytes(int64_t n, const dwg_kernel_params* kp, const dwg_mc_params* mcp, int64_t cells) {
+  McParams mp;
+  if (check_mcp(mcp, n, &mp) != DWG_OK || check_kp(kp) != DWG_OK || cells < 0) return 0;
+  const dwg_kernel_params k = kp ? *kp : kDefaultKp;
+  return align256(mc_bytes(n, k, mp, cells));
+}
+
+dwg_status dwg_mc_cells(const float* P, int64_t n, const dwg_mc_params* mcp, int64_t* cells, void* ws,
+                        size_t ws_bytes, void* stream) {
+  if (cells) *cells = 0;
+  DWG_CHECK(P && cells, "P and cells must not be NULL");
+  McParams mp;
+  DWG_PROPAGATE(check_mcp(mcp, n, &mp));
+  const size_t need = mc_bytes(n, kDefaultKp, mp, 0);
+  DWG_CHECK(ws || ws_bytes == 0, "ws is NULL but ws_bytes > 0");
+  if (!ws || ws_bytes < need) {
+    set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+    return DWG_E_WORKSPACE;
+  }
+  DWG_PROPAGATE(check_device());
+  Carver c(ws);
+  McWork w;
+  carve_mc_grid(c, n, mp, &w);
+  return mc_cells(P, n, mp, w, cells, static_cast<hipStream_t>(stream));
+}
+
+dwg_status dwg_iterate_mc(const float* P, const float* area, const float* delta, int64_t n, float* N_inout,
+                          const dwg_kernel_params* kpp, const dwg_iterate_params* ip, const dwg_mc_params* mcp,
+                          dwg_iter_stat* stats_host, int* iters_done, void* ws, size_t ws_bytes, void* stream) {
+  if (iters_done) *iters_done = 0;
+  DWG_CHECK(P && area && N_inout && ip, "P, area, N_inout and ip must not be NULL");
+  DWG_CHECK(ip->max_iters >= 1, "max_iters must be >= 1");
+  DWG_CHECK(ip->fixed_iters == 0 || ip->fixed_iters == 1, "fixed_iters must be 0 or 1");
+  DWG_CHECK(std::isfinite(ip->eps_deg) && ip->eps_deg >= 0.0, "eps_deg must be finite and >= 0");
+  DWG_CHECK(ip->top_frac > 0.0 && ip->top_frac <= 1.0, "top_frac must be in (0, 1]");
+  McParams mp;
+  DWG_PROPAGATE(check_mcp(mcp, n, &mp));
+  DWG_PROPAGATE(check_kp(kpp));
+  const dwg_kernel_params kp = kpp ? *kpp : kDefaultKp;
+  const size_t need0 = mc_bytes(n, kp, mp, 0);
+  DWG_CHECK(ws || ws_bytes == 0, "ws is NULL but ws_bytes > 0");
+  if (!ws || ws_bytes < need0) {
+    set_error("workspace too small: %zu bytes given, at least %zu needed", ws_bytes, need0);
+    return DWG_E_WORKSPACE;
+  }
+  DWG_PROPAGATE(check_device());
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  McWork w;
+  EvalState es;
+  DWG_PROPAGATE(mc_prepare(P, N_inout, area, delta, n, kp, mp, ws, ws_bytes, st, &w, &es));
+  EventPair ev;
+  DWG_PROPAGATE(ev.create());
+  dwg_status result = DWG_NOT_CONVERGED;
+  for (int t = 0; t < ip->max_iters; ++t) {
+    DWG_TRY_HIP(hipEventRecord(ev.a, st));
+    DWG_PROPAGATE(mc_field(kp, mp, w, es, st));
+    DWG_TRY_HIP(hipEventRecord(ev.b, st));
+    int64_t F = 0;
+    DWG_PROPAGATE(mc_faces(w, nullptr, 0, &F, st));
+    DWG_PROPAGATE(mc_scatter(mp, w, F, st));
+    DWG_PROPAGATE(mc_update(mp, w, es.wk, N_inout, st));
+    DWG_PROPAGATE(launch_stats(n, ip->top_frac, es.wk, st));
+    DWG_TRY_HIP(hipMemcpyAsync(es.wk.stats, w.iso, sizeof(double), hipMemcpyDeviceToDevice, st));
+    double hs[4];
+    DWG_TRY_HIP(hipMemcpyAsync(hs, es.wk.stats, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    DWG_TRY_HIP(hipStreamSynchronize(st));
+    float kms = 0.0f;
+    DWG_TRY_HIP(hipEventElapsedTime(&kms, ev.a, ev.b));
+    if (stats_host) {
+      stats_host[t].wmean = hs[0];
+      stats_host[t].top_mean_deg = hs[1];
+      stats_host[t].mean_chord = hs[2];
+      stats_host[t].gwn_ms = (double)kms;
+    }
+    if (iters_done) *iters_done = t + 1;
+    if (!std::isfinite(hs[0]) || !std::isfinite(hs[1]) || !std::isfinite(hs[2])) {
+      set_error("non-finite statistics at iteration %d (wmean=%g, top=%g, chord=%g)", t + 1, hs[0], hs[1], hs[2]);
+      return DWG_E_NONFINITE;
+    }
+    if (ip->fixed_iters) {
+      result = DWG_OK;
+    } else if (hs[1] <= ip->eps_deg) {
+      result = DWG_OK;
+      break;
+    }
+  }
+  if (ip->fixed_iters) result = DWG_OK;
+  return result;
+}
+
+dwg_status dwg_level_set(const float* P, const float* N, const float* area, const float* delta, int64_t n,
+                         const dwg_kernel_params* kpp, const dwg_mc_params* mcp, float* tri, int64_t cap,
+                         int64_t* ntri, double* iso, void* ws, size_t ws_bytes, void* stream) {
+  if (ntri) *ntri = 0;
+  DWG_CHECK(P && N && area && tri && ntri && iso, "P, N, area, tri, ntri and iso must not be NULL");
+  DWG_CHECK(cap >= 1, "cap must be >= 1");
+  McParams mp;
+  DWG_PROPAGATE(check_mcp(mcp, n, &mp));
+  DWG_PROPAGATE(check_kp(kpp));
+  const dwg_kernel_params kp = kpp ? *kpp : kDefaultKp;
+  const size_t need0 = mc_bytes(n, kp, mp, 0);
+  DWG_CHECK(ws || ws_bytes == 0, "ws is NULL but ws_bytes > 0");
+  if (!ws || ws_bytes < need0) {
+    set_error("workspace too small: %zu bytes given, at least %zu needed", ws_bytes, need0);
+    return DWG_E_WORKSPACE;
+  }
+  DWG_PROPAGATE(check_device());
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  McWork w;
+  EvalState es;
+  DWG_PROPAGATE(mc_prepare(P, N, area, delta, n, kp, mp, ws, ws_bytes, st, &w, &es));
+  DWG_PROPAGATE(mc_field(kp, mp, w, es, st));
+  int64_t F = 0;
+  DWG_PROPAGATE(mc_faces(w, tri, cap, &F, st));
+  DWG_TRY_HIP(hipMemcpyAsync(iso, w.iso, sizeof(double), hipMemcpyDeviceToHost, st));
+  DWG_TRY_HIP(hipStreamSynchronize(st));
+  *ntri = F;
+  if (F > cap) {
+    set_error("level set has %lld triangles, output holds %lld", (long long)F, (long long)cap);
+    return DWG_E_INVALID;
+  }
+  return DWG_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
 dwg_status dwg_octree(const float* P, int64_t n, int leaf, int32_t* perm, int32_t* nodes, int64_t cap,
                       int64_t* count, void* ws, size_t ws_bytes, void* stream) {
   if (count) *count = 0;

@@ -177,6 +177,74 @@ dwg_status tree_eval(const float* Q, int64_t m, const dwg_kernel_params& kp, boo
                      const TreeWork& t, hipStream_t st);
 dwg_status tree_export(const TreeWork& t, int32_t* nodes_out, int64_t cap_out, int64_t* count_host,
                        hipStream_t st);
+// Stable LSD radix sort of (key, value) pairs on the low `bits` bits, 8 bits per pass,
+// ping-ponging between key[0]/val[0] and key[1]/val[1]; *result = the buffer holding the
+// sorted pairs. hist needs radix_hist_len(n) ints, hsums scan_sums_len(radix_hist_len(n)).
+size_t radix_hist_len(int64_t n);
+dwg_status radix_sort_pairs(uint64_t* const key[2], int32_t* const val[2], int64_t n, int bits, int32_t* hist,
+                            int32_t* hsums, int* result, hipStream_t st);
+// Bounding box of P and the octree frame (lo xyz, 2^21 / largest extent) in FP64.
+dwg_status morton_frame(const float* P, int64_t n, float* bpart, float* box, double* frame, hipStream_t st);
+// Uniform-grid kNN over reference points: build once, then query [q0, q0 + m) of a planar
+// query array with leading dimension qld (no skipping).
+dwg_status knn_grid(const float* R, int64_t nr, const KnnWork& w, hipStream_t st);
+dwg_status knn_search(const float* Q, int64_t qld, int64_t q0, int64_t m, const KnnWork& w, int k, int32_t* idx,
+                      float* dist, hipStream_t st);
+
+// The paper's level-set update (dwg_mc.hip): grid cells and corners, faces, scatter.
+struct McParams {
+  int depth;       // grid cells per axis = 2^depth
+  int dilate;      // rings of neighbour cells added around the cells holding points
+  int k;           // nearest points per face
+  int iso_points;  // 1: w_bar = mean of w over the input points; 0: over the grid corners
+};
+struct McWork {
+  // grid phase (sized by n)
+  float* bpart;
+  float* box;
+  double* frame;           // octree frame: lo xyz, 2^21 / side
+  uint64_t* key[2];        // [kcap] radix-sort ping-pong
+  int32_t* val[2];
+  int32_t* hist;
+  int32_t* hsums;
+  int32_t* head;           // [kcap + 1] run heads, then their exclusive scan
+  int32_t* hdsums;
+  uint64_t* occ;           // [n] occupied cell codes
+  uint64_t* cells;         // [kcap] evaluated cell codes (Morton order)
+  // faces phase (sized by the cell count C)
+  uint64_t* ckey[2];       // [8C] corner keys
+  int32_t* cval[2];
+  int32_t* chist;
+  int32_t* chsums;
+  int32_t* chead;          // [8C + 1]
+  int32_t* chdsums;
+  int32_t* cidx;           // [C][8] corner id of each cell corner
+  float* pos;              // [3][ld] corner positions, then the points when w_bar is taken over them
+  float* wc;               // [ld] w at those queries
+  double* iso;             // [1] w_bar
+  double* ipart;           // [256] partial sums of w_bar
+  int32_t* fcnt;           // [C + 1] faces per cell, then their exclusive scan
+  int32_t* fsums;
+  float* cen;              // [3][fcap] face centroids
+  float4* vec;             // [fcap] face vectors
+  int32_t* idx;            // [chunk][k] nearest points of a chunk of faces
+  float* dist;
+  unsigned long long* acc; // [n][3] fixed-point face sums
+  KnnWork knn;             // uniform grid over the points
+  int64_t n = 0, kcap = 0, C = 0, m = 0, ld = 0, mcap = 0, fcap = 0, chunk = 0;
+};
+int64_t mc_key_cap(int64_t n, const McParams& mp);
+size_t carve_mc_grid(Carver& c, int64_t n, const McParams& mp, McWork* out);
+size_t carve_mc_faces(Carver& c, int64_t n, int64_t C, int k, McWork* w);
+dwg_status mc_cells(const float* P, int64_t n, const McParams& mp, const McWork& w, int64_t* C_host,
+                    hipStream_t st);
+dwg_status mc_corners(const McParams& mp, McWork& w, int64_t* m_host, hipStream_t st);
+dwg_status mc_faces(const McWork& w, float* tri, int64_t tcap, int64_t* F_host, hipStream_t st);
+dwg_status mc_scatter(const McParams& mp, const McWork& w, int64_t F, hipStream_t st);
+dwg_status mc_clear(const McWork& w, hipStream_t st);
+dwg_status mc_append_points(const float* P, int64_t n, const McWork& w, hipStream_t st);
+dwg_status mc_point_iso(const McWork& w, const float* w_points, int64_t n, hipStream_t st);
+dwg_status mc_update(const McParams& mp, const McWork& w, const GwnWork& g, float* N, hipStream_t st);
 
 // Workspace bytes of the kNN / features / MLP stages for n points.
 size_t knn_ws_bytes(int64_t n_ref, int64_t n_qry);

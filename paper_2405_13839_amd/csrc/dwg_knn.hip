@@ -618,6 +618,13 @@ dwg_status knn_query(const float* Q, int64_t qld, int64_t q0, int64_t m, const K
 
 }  // namespace
 
+dwg_status knn_grid(const float* R, int64_t nr, const KnnWork& w, hipStream_t st) { return build_grid(R, nr, w, st); }
+
+dwg_status knn_search(const float* Q, int64_t qld, int64_t q0, int64_t m, const KnnWork& w, int k, int32_t* idx,
+                      float* dist, hipStream_t st) {
+  return knn_query(Q, qld, q0, m, w, 0, 1, k, idx, dist, st);
+}
+
 size_t carve_knn(Carver& c, int64_t nr, KnnWork* out) {
   const int64_t mc = max_cells_for(nr);
   const size_t s0 = c.used;

@@ -620,6 +620,34 @@ void launch_eval_t(const float* Q, int64_t m, const int32_t* qperm, const GwnWor
 
 int64_t tree_cap(int64_t n) { return 2 * n + 1; }
 
+size_t radix_hist_len(int64_t n) { return (size_t)(256 * cdiv(n, kSortTile) + 1); }
+
+dwg_status radix_sort_pairs(uint64_t* const key[2], int32_t* const val[2], int64_t n, int bits, int32_t* hist,
+                            int32_t* hsums, int* result, hipStream_t st) {
+  const int64_t nsb = cdiv(n, kSortTile);
+  const int passes = (bits + 7) / 8;
+  for (int pass = 0; pass < passes; ++pass) {
+    const int a = pass & 1, b = a ^ 1;
+    hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nsb), dim3(256), 0, st, key[a], n, 8 * pass, hist, nsb);
+    DWG_TRY_LAUNCH();
+    dwg_status s = exclusive_scan(hist, 256 * nsb, hsums, st);
+    if (s != DWG_OK) return s;
+    hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nsb), dim3(256), 0, st, key[a], val[a], n, 8 * pass, hist, nsb,
+                       key[b], val[b]);
+    DWG_TRY_LAUNCH();
+  }
+  *result = passes & 1;
+  return DWG_OK;
+}
+
+dwg_status morton_frame(const float* P, int64_t n, float* bpart, float* box, double* frame, hipStream_t st) {
+  dwg_status s = launch_bbox(P, n, bpart, box, st);
+  if (s != DWG_OK) return s;
+  hipLaunchKernelGGL(k_tree_frame, dim3(1), dim3(64), 0, st, box, frame);
+  DWG_TRY_LAUNCH();
+  return DWG_OK;
+}
+
 size_t carve_tree(Carver& c, int64_t n, int leaf, double beta, TreeWork* out) {
   const size_t s0 = c.used;
   TreeWork t{};
@@ -660,21 +688,13 @@ size_t carve_tree(Carver& c, int64_t n, int leaf, double beta, TreeWork* out) {
 
 dwg_status tree_build(const float* P, const float* area, const float* delta, int64_t n, float eps,
                       const TreeWork& t, int32_t* perm, hipStream_t st) {
-  dwg_status s = launch_bbox(P, n, t.bpart, t.box, st);
+  dwg_status s = morton_frame(P, n, t.bpart, t.box, t.frame, st);
   if (s != DWG_OK) return s;
-  hipLaunchKernelGGL(k_tree_frame, dim3(1), dim3(64), 0, st, t.box, t.frame);
   hipLaunchKernelGGL(k_tree_keys, dim3(grid_cap(n)), dim3(256), 0, st, P, n, t.frame, t.key[0], t.val[0]);
   DWG_TRY_LAUNCH();
-  for (int pass = 0; pass < 8; ++pass) {
-    const int a = pass & 1, b = a ^ 1;
-    hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)t.nsb), dim3(256), 0, st, t.key[a], n, 8 * pass, t.hist, t.nsb);
-    DWG_TRY_LAUNCH();
-    s = exclusive_scan(t.hist, 256 * t.nsb, t.hsums, st);
-    if (s != DWG_OK) return s;
-    hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)t.nsb), dim3(256), 0, st, t.key[a], t.val[a], n, 8 * pass,
-                       t.hist, t.nsb, t.key[b], t.val[b]);
-    DWG_TRY_LAUNCH();
-  }
+  int res = 0;
+  s = radix_sort_pairs(t.key, t.val, n, 64, t.hist, t.hsums, &res, st);
+  if (s != DWG_OK) return s;
   // eight passes: the sorted codes and indices are back in buffer 0
   hipLaunchKernelGGL(k_tree_mark, dim3(grid_cap(n)), dim3(256), 0, st, t.key[0], n, t.leaf, t.lev, t.off);
   DWG_TRY_LAUNCH();

@@ -40,6 +40,10 @@ class IterateParams(ctypes.Structure):
                 ("top_frac", ctypes.c_double)]
 
 
+class McParams(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int), ("dilate", ctypes.c_int), ("k", ctypes.c_int), ("iso", ctypes.c_int)]
+
+
 class IterStat(ctypes.Structure):
     _fields_ = [("wmean", ctypes.c_double), ("top_mean_deg", ctypes.c_double), ("mean_chord", ctypes.c_double),
                 ("gwn_ms", ctypes.c_double)]
@@ -75,13 +79,22 @@ def load():
     lib.dwg_mlp_param_count.restype = i64
     lib.dwg_octree.argtypes = [vp, i64, i32, vp, vp, i64, ctypes.POINTER(i64), vp, sz, vp]
     lib.dwg_delta_knn_window.argtypes = [vp, i64, i32, f32, f32, vp, vp, sz, vp]
+    mcpp = ctypes.POINTER(McParams)
+    lib.dwg_mc_workspace_bytes.restype = sz
+    lib.dwg_mc_workspace_bytes.argtypes = [i64, kpp, mcpp, i64]
+    lib.dwg_mc_cells.argtypes = [vp, i64, mcpp, ctypes.POINTER(i64), vp, sz, vp]
+    lib.dwg_iterate_mc.argtypes = [vp, vp, vp, i64, vp, kpp, ctypes.POINTER(IterateParams), mcpp,
+                                   ctypes.POINTER(IterStat), ctypes.POINTER(ctypes.c_int), vp, sz, vp]
+    lib.dwg_level_set.argtypes = [vp, vp, vp, vp, i64, kpp, mcpp, vp, i64, ctypes.POINTER(i64),
+                                  ctypes.POINTER(ctypes.c_double), vp, sz, vp]
     lib.dwg_voronoi_area.argtypes = [vp, i64, i32, vp, vp, sz, vp]
     lib.dwg_features.argtypes = [vp, i64, i64, vp, vp, sz, vp]
     lib.dwg_mlp_infer.argtypes = [vp, vp, i64, vp, vp, sz, vp]
     lib.dwg_mlp_train_step.argtypes = [vp, vp, vp, i64, f32, vp, vp, vp, i64, vp, vp, vp, sz, vp]
     for name in ["dwg_gwn_eval", "dwg_gwn_grad", "dwg_iterate", "dwg_init_normals", "dwg_knn",
                  "dwg_delta_knn_mean", "dwg_delta_anchor_mean", "dwg_features", "dwg_mlp_infer",
-                 "dwg_mlp_train_step", "dwg_octree", "dwg_delta_knn_window", "dwg_voronoi_area"]:
+                 "dwg_mlp_train_step", "dwg_octree", "dwg_delta_knn_window", "dwg_voronoi_area", "dwg_mc_cells",
+                 "dwg_iterate_mc", "dwg_level_set"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -90,7 +103,8 @@ def load():
 EXPORTED = ["dwg_version", "dwg_status_string", "dwg_last_error", "dwg_workspace_bytes", "dwg_gwn_eval",
             "dwg_gwn_grad", "dwg_iterate", "dwg_init_normals", "dwg_knn", "dwg_delta_knn_mean",
             "dwg_delta_anchor_mean", "dwg_mlp_param_count", "dwg_features", "dwg_mlp_infer",
-            "dwg_mlp_train_step", "dwg_octree", "dwg_delta_knn_window", "dwg_voronoi_area"]
+            "dwg_mlp_train_step", "dwg_octree", "dwg_delta_knn_window", "dwg_voronoi_area", "dwg_mc_workspace_bytes",
+            "dwg_mc_cells", "dwg_iterate_mc", "dwg_level_set"]
 
 
 def version() -> str:
@@ -202,6 +216,83 @@ def iterate(P, area, delta, N, params: Params | None = None, max_iters=50, fixed
     out = torch.tensor([[s.wmean, s.top_mean_deg, s.mean_chord, s.gwn_ms] for s in stats[: done.value]],
                        dtype=torch.float64).reshape(-1, 4)
     return st, out
+
+
+def mc_workspace(P, params: Params | None = None, depth: int = 8, dilate: int = 1, k: int = 10,
+                 iso: str = "points") -> torch.Tensor:
+    """Workspace for iterate_mc / level_set on P: sized for the actual number of grid cells."""
+    lib = load()
+    P = _dev(P, "P")
+    n = P.shape[1]
+    kp = (params or Params()).c()
+    mp = McParams(int(depth), int(dilate), int(k), _iso(iso))
+    g = int(lib.dwg_mc_workspace_bytes(n, ctypes.byref(kp), ctypes.byref(mp), 0))
+    if g == 0:
+        raise DwgError(DWG_E_INVALID, "DWG_E_INVALID", "invalid level-set parameters")
+    gws = torch.empty(g, dtype=torch.uint8, device=P.device)
+    cells = ctypes.c_int64(0)
+    _check(lib.dwg_mc_cells(_ptr(P), n, ctypes.byref(mp), ctypes.byref(cells), _ptr(gws), gws.numel(),
+                            _stream(P.device)))
+    del gws
+    total = int(lib.dwg_mc_workspace_bytes(n, ctypes.byref(kp), ctypes.byref(mp), cells.value))
+    return torch.empty(total, dtype=torch.uint8, device=P.device)
+
+
+def _iso(iso: str) -> int:
+    if iso not in ("points", "corners"):
+        raise ValueError("iso must be 'points' or 'corners'")
+    return 0 if iso == "points" else 1
+
+
+def iterate_mc(P, area, delta, N, params: Params | None = None, depth=8, dilate=1, k=10, max_iters=50,
+               fixed_iters=False, eps_deg=0.1, top_frac=0.01, ws=None, iso: str = "points"):
+    """Algorithm 1 with the paper's level-set update, in place on N. Returns (status, stats
+    float64 [T, 4]): per iteration w_bar (over the points, or the grid corners with
+    iso='corners'), top-1% mean angle change, mean chord, evaluation ms."""
+    lib = load()
+    params = params or Params()
+    P = _dev(P, "P")
+    n = P.shape[1]
+    _dev(area, "area", shape=(n,))
+    if delta is not None:
+        _dev(delta, "delta", shape=(n,))
+    _dev(N, "N", shape=(3, n))
+    if ws is None:
+        ws = mc_workspace(P, params, depth, dilate, k, iso)
+    kp = params.c()
+    mp = McParams(int(depth), int(dilate), int(k), _iso(iso))
+    ip = IterateParams(int(max_iters), int(bool(fixed_iters)), float(eps_deg), float(top_frac))
+    stats = (IterStat * int(max_iters))()
+    done = ctypes.c_int(0)
+    st = lib.dwg_iterate_mc(_ptr(P), _ptr(area), _ptr(delta), n, _ptr(N), ctypes.byref(kp), ctypes.byref(ip),
+                            ctypes.byref(mp), stats, ctypes.byref(done), _ptr(ws), ws.numel(), _stream(P.device))
+    _check(st, ok=(DWG_OK, DWG_NOT_CONVERGED))
+    out = torch.tensor([[s.wmean, s.top_mean_deg, s.mean_chord, s.gwn_ms] for s in stats[: done.value]],
+                       dtype=torch.float64).reshape(-1, 4)
+    return st, out
+
+
+def level_set(P, N, area, delta, params: Params | None = None, depth=8, dilate=1, ws=None, iso: str = "points"):
+    """The w_bar level set: (triangles float32 [F, 3, 3] wound outwards, w_bar)."""
+    lib = load()
+    params = params or Params()
+    P = _dev(P, "P")
+    n = P.shape[1]
+    if ws is None:
+        ws = mc_workspace(P, params, depth, dilate, 10, iso)
+    kp = params.c()
+    mp = McParams(int(depth), int(dilate), 10, _iso(iso))
+    ntri = ctypes.c_int64(0)
+    iso = ctypes.c_double(0.0)
+    tri = torch.empty((1, 9), dtype=torch.float32, device=P.device)
+    args = lambda t: (_ptr(P), _ptr(N), _ptr(area), _ptr(delta), n, ctypes.byref(kp), ctypes.byref(mp), _ptr(t),
+                      t.shape[0], ctypes.byref(ntri), ctypes.byref(iso), _ptr(ws), ws.numel(), _stream(P.device))
+    st = lib.dwg_level_set(*args(tri))
+    if st == DWG_E_INVALID and ntri.value > 1:
+        tri = torch.empty((ntri.value, 9), dtype=torch.float32, device=P.device)
+        st = lib.dwg_level_set(*args(tri))
+    _check(st)
+    return tri[: ntri.value].reshape(-1, 3, 3), iso.value
 
 
 def random_normals(n: int, seed: int, device) -> torch.Tensor:
