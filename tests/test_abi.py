@@ -100,6 +100,39 @@ def test_knn_and_mlp_validation():
     assert dwg.mlp_param_count() == 128 * 48 + 128 + 128 * 128 + 128 + 3 * 128 + 3
 
 
+def test_octree_area_and_level_set_validation():
+    lib = dwg.load()
+    cnt = ctypes.c_int64(5)
+    assert lib.dwg_octree(FAKE, 0, 0, FAKE, FAKE, 10, ctypes.byref(cnt), FAKE, 1 << 40, None) == dwg.DWG_E_INVALID
+    assert cnt.value == 0
+    assert lib.dwg_octree(FAKE, 100, 2000, FAKE, FAKE, 10, ctypes.byref(cnt), FAKE, 1 << 40, None) == dwg.DWG_E_INVALID
+    assert lib.dwg_octree(FAKE, 100, 0, FAKE, FAKE, 200, ctypes.byref(cnt), FAKE, 64, None) == dwg.DWG_E_WORKSPACE
+    assert lib.dwg_voronoi_area(FAKE, 100, 2, FAKE, FAKE, 1 << 40, None) == dwg.DWG_E_INVALID
+    assert lib.dwg_voronoi_area(FAKE, 10, 15, FAKE, FAKE, 1 << 40, None) == dwg.DWG_E_INVALID
+    assert lib.dwg_delta_knn_window(FAKE, 100, 10, 0.5, 0.1, FAKE, FAKE, 1 << 40, None) == dwg.DWG_E_INVALID
+    assert lib.dwg_init_normals(dwg.INIT_PCA, 0, FAKE, 16, None, FAKE, FAKE, 1 << 40, None) == dwg.DWG_E_INVALID
+    assert lib.dwg_init_normals(dwg.INIT_GAUSS, 0, None, 16, None, FAKE, None, 0, None) == dwg.DWG_E_INVALID
+    kp = dwg.Params().c()
+    ip = dwg.IterateParams(5, 0, 0.1, 0.01)
+    for mp in [dwg.McParams(0, 1, 10, 0), dwg.McParams(17, 1, 10, 0), dwg.McParams(8, 3, 10, 0),
+               dwg.McParams(8, 1, 0, 0), dwg.McParams(8, 1, 17, 0), dwg.McParams(8, 1, 10, 2)]:
+        assert lib.dwg_mc_workspace_bytes(1000, ctypes.byref(kp), ctypes.byref(mp), 0) == 0
+        done = ctypes.c_int(3)
+        assert lib.dwg_iterate_mc(FAKE, FAKE, None, 1000, FAKE, ctypes.byref(kp), ctypes.byref(ip), ctypes.byref(mp),
+                                  None, ctypes.byref(done), FAKE, 1 << 40, None) == dwg.DWG_E_INVALID
+        assert done.value == 0
+    good = dwg.McParams(8, 1, 10, 0)
+    g = lib.dwg_mc_workspace_bytes(1000, ctypes.byref(kp), ctypes.byref(good), 0)
+    assert g > 0 and lib.dwg_mc_workspace_bytes(1000, ctypes.byref(kp), ctypes.byref(good), 500) > g
+    cells = ctypes.c_int64(9)
+    assert lib.dwg_mc_cells(FAKE, 1000, ctypes.byref(good), ctypes.byref(cells), FAKE, 64, None) == dwg.DWG_E_WORKSPACE
+    assert cells.value == 0
+    ntri, iso = ctypes.c_int64(4), ctypes.c_double(0.0)
+    assert lib.dwg_level_set(FAKE, FAKE, FAKE, None, 1000, ctypes.byref(kp), ctypes.byref(good), FAKE, 0,
+                             ctypes.byref(ntri), ctypes.byref(iso), FAKE, 1 << 40, None) == dwg.DWG_E_INVALID
+    assert ntri.value == 0
+
+
 def test_single_hip_runtime_in_process():
     """libdwg must bind to the HIP runtime torch already loaded (one libamdhip64 mapped)."""
     dwg.load()

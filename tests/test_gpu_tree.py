@@ -139,3 +139,25 @@ def test_tree_full_size_sampled_1M():
     print(f"[tree] 1M: e_w={ew:.2e} e_g={eg:.2e} flagged={int((~ok).sum())}; octree vs exact on 50 queries: "
           f"e_w={e_w(wg[:50], w_ex):.2e} e_g={e_g(gg[:, :50], g_ex):.2e}")
     assert ew <= TOL_W and eg <= TOL_G
+
+
+def test_tree_trajectory_matches_oracle():
+    """Ten Jacobi iterations in octree mode from random normals on the C1 sphere (2,000
+    points, plain kernel) against the oracle iterating its own octree evaluation: the
+    normals stay together (a decision on a flagged query can move one normal slightly)."""
+    from tests.helpers import angle_deg
+    dwg = _dwg()
+    s = synth.sphere(2000, 0.005, 100)
+    N0 = oracle.random_normals(200, s.n)
+    d = oracle.delta(s.P, 10) * 2.0
+    Nt = cuda(N0.astype(np.float32))
+    st, stats = dwg.iterate(cuda(s.P), cuda(s.area), cuda(d.astype(np.float32)), Nt, dwg.Params(beta=2.3, leaf=8),
+                            max_iters=10, fixed_iters=True)
+    N = N0.astype(np.float32).astype(np.float64)
+    for t in range(10):
+        w, g, _ = oracle.tree_gwn(s.P, N, s.area, d.astype(np.float32), s.P, beta=2.3, leaf=8)
+        N, _ = oracle.update(g, N)
+        N = N.astype(np.float32).astype(np.float64)  # the GPU keeps FP32 normals between iterations
+        assert abs(stats[t, 0].item() - w.mean()) <= 1e-5
+    ang = angle_deg(host(Nt), N)
+    assert np.median(ang) <= 1e-3 and np.mean(ang <= 0.05) >= 0.995, np.percentile(ang, [50, 99, 100])
