@@ -2,10 +2,12 @@
 
     python -m paper_2405_13839_amd.profiling gwn  --n 1000000 --lam 10 --reps 2
     python -m paper_2405_13839_amd.profiling tree --n 1000000 --lam 10 --reps 5
+    python -m paper_2405_13839_amd.profiling mc   --n 1000000 --lam 10 --reps 5
     python -m paper_2405_13839_amd.profiling copy --mib 1024 --reps 3
 
 `gwn` launches the all-pairs kernel through dwg_gwn_grad on the C3 workload shape; `tree`
-runs dwg_iterate in octree mode (beta 2.3, anchor radius, fixed iterations) on it; `copy`
+runs dwg_iterate in octree mode (beta 2.3, anchor radius, fixed iterations) on it; `mc` runs
+dwg_iterate_mc (the level-set update, depth 8, octree evaluation) on it; `copy`
 runs a plain device-to-device copy of a known size, used to calibrate the FETCH_SIZE /
 WRITE_SIZE counters (bytes the counters report per byte actually moved).
 """
@@ -17,7 +19,7 @@ import sys
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["gwn", "copy", "iterate", "tree"])
+    ap.add_argument("what", choices=["gwn", "copy", "iterate", "tree", "mc"])
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--lam", type=float, default=10.0)
     ap.add_argument("--reps", type=int, default=2)
@@ -40,9 +42,9 @@ def main(argv=None) -> int:
     c = synth.torus_ellipsoids(args.n, seed=102)
     P = torch.from_numpy(c.P).to(dev)
     a = torch.from_numpy(c.area).to(dev)
-    prm = dwg.Params(lam=args.lam, beta=2.3 if args.what == "tree" else 0.0)
+    prm = dwg.Params(lam=args.lam, beta=2.3 if args.what in ("tree", "mc") else 0.0)
     ws = dwg.workspace(c.n, c.n, dev, prm)
-    if args.what == "tree":
+    if args.what in ("tree", "mc"):
         d = dwg.delta_anchor_mean(P, 10, 4096, 1.0, ws=ws)
     else:
         d = dwg.delta_knn_mean(P, 10, 2.0, ws=ws)
@@ -51,6 +53,10 @@ def main(argv=None) -> int:
         for _ in range(args.reps):
             dwg.gwn(P, N, a, d, P, prm, ws=ws)
         torch.cuda.synchronize()
+    elif args.what == "mc":
+        del ws
+        st, stats = dwg.iterate_mc(P, a, d, N, prm, depth=8, dilate=1, k=10, max_iters=args.reps, fixed_iters=True)
+        print("evaluation ms per iteration:", np.round(stats[:, 3].numpy(), 3).tolist())
     else:  # iterate / tree
         st, stats = dwg.iterate(P, a, d, N, prm, max_iters=args.reps, fixed_iters=True, ws=ws)
         print("kernel ms per iteration:", np.round(stats[:, 3].numpy(), 3).tolist())
