@@ -177,6 +177,61 @@ dwg_status gwn_common(const float* P, const float* N, const float* area, const f
   return DWG_OK;
 }
 
+dwg_status check_mcp(const dwg_mc_params* mcp, int64_t n, McParams* out) {
+  DWG_CHECK(mcp, "mcp must not be NULL");
+  DWG_CHECK(mcp->depth >= 1 && mcp->depth <= 16, "depth must be in [1, 16]");
+  DWG_CHECK(mcp->dilate >= 0 && mcp->dilate <= 2, "dilate must be in [0, 2]");
+  DWG_CHECK(mcp->k >= 1 && mcp->k <= kMaxK, "k must be in [1, %d]", kMaxK);
+  DWG_CHECK(mcp->iso == 0 || mcp->iso == 1, "iso must be 0 (points) or 1 (grid corners)");
+  const int64_t w = 2 * mcp->dilate + 1;
+  DWG_CHECK(n > mcp->k && n * w * w * w < (int64_t(1) << 31), "need k < n < 2^31 / (2 dilate + 1)^3");
+  *out = McParams{mcp->depth, mcp->dilate, mcp->k, mcp->iso == 0 ? 1 : 0};
+  return DWG_OK;
+}
+
+size_t mc_bytes(int64_t n, const dwg_kernel_params& kp, const McParams& mp, int64_t cells) {
+  Carver c(nullptr);
+  carve_mc_grid(c, n, mp, nullptr);
+  if (cells > 0) {
+    carve_mc_faces(c, n, cells, mp.k, nullptr);
+    c.used = align256(c.used + gwn_bytes(n, 8 * cells + (mp.iso_points ? n : 0), kp));
+  }
+  return c.used;
+}
+
+// Grid, corners and the evaluation state of the level-set update; checks the workspace
+// against the actual cell count.
+dwg_status mc_prepare(const float* P, const float* N, const float* area, const float* delta, int64_t n,
+                      const dwg_kernel_params& kp, const McParams& mp, void* ws, size_t ws_bytes, hipStream_t st,
+                      McWork* w, EvalState* es) {
+  Carver c(ws);
+  carve_mc_grid(c, n, mp, w);
+  int64_t C = 0;
+  DWG_PROPAGATE(mc_cells(P, n, mp, *w, &C, st));
+  const size_t need = mc_bytes(n, kp, mp, C);
+  if (ws_bytes < need) {
+    set_error("workspace too small for %lld grid cells: %zu bytes given, %zu needed", (long long)C, ws_bytes, need);
+    return DWG_E_WORKSPACE;
+  }
+  DWG_CHECK(12 * C < (int64_t(1) << 31), "too many grid cells (%lld)", (long long)C);
+  carve_mc_faces(c, n, C, mp.k, w);
+  int64_t m = 0;
+  DWG_PROPAGATE(mc_corners(mp, *w, &m, st));
+  if (mp.iso_points) DWG_PROPAGATE(mc_append_points(P, n, *w, st));
+  DWG_PROPAGATE(knn_grid(P, n, w->knn, st));
+  DWG_PROPAGATE(mc_clear(*w, st));
+  return eval_prepare(P, N, area, delta, n, w->pos, w->ld, kp, false, static_cast<char*>(ws) + c.used, st, es);
+}
+
+// w at the corners (and at the points when w_bar is taken over them) and w_bar.
+dwg_status mc_field(const dwg_kernel_params& kp, const McParams& mp, const McWork& w, const EvalState& es,
+                    hipStream_t st) {
+  DWG_PROPAGATE(eval_run(w.pos, w.ld, kp, false, es, st));
+  if (!mp.iso_points) return launch_combine(w.ld, kp, false, w.wc, nullptr, w.iso, es.wk, st);
+  DWG_PROPAGATE(launch_combine(w.ld, kp, false, w.wc, nullptr, nullptr, es.wk, st));
+  return mc_point_iso(w, w.wc + w.m, w.n, st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -282,69 +337,6 @@ dwg_status dwg_iterate(const float* P, const float* area, const float* delta, in
   if (ip->fixed_iters) result = DWG_OK;
   return result;
 }
-
-}  // extern "C"
-
-namespace {
-
-dwg_status check_mcp(const dwg_mc_params* mcp, int64_t n, McParams* out) {
-  DWG_CHECK(mcp, "mcp must not be NULL");
-  DWG_CHECK(mcp->depth >= 1 && mcp->depth <= 16, "depth must be in [1, 16]");
-  DWG_CHECK(mcp->dilate >= 0 && mcp->dilate <= 2, "dilate must be in [0, 2]");
-  DWG_CHECK(mcp->k >= 1 && mcp->k <= kMaxK, "k must be in [1, %d]", kMaxK);
-  DWG_CHECK(mcp->iso == 0 || mcp->iso == 1, "iso must be 0 (points) or 1 (grid corners)");
-  const int64_t w = 2 * mcp->dilate + 1;
-  DWG_CHECK(n > mcp->k && n * w * w * w < (int64_t(1) << 31), "need k < n < 2^31 / (2 dilate + 1)^3");
-  *out = McParams{mcp->depth, mcp->dilate, mcp->k, mcp->iso == 0 ? 1 : 0};
-  return DWG_OK;
-}
-
-size_t mc_bytes(int64_t n, const dwg_kernel_params& kp, const McParams& mp, int64_t cells) {
-  Carver c(nullptr);
-  carve_mc_grid(c, n, mp, nullptr);
-  if (cells > 0) {
-    carve_mc_faces(c, n, cells, mp.k, nullptr);
-    c.used = align256(c.used + gwn_bytes(n, 8 * cells + (mp.iso_points ? n : 0), kp));
-  }
-  return c.used;
-}
-
-// Grid, corners and the evaluation state of the level-set update; checks the workspace
-// against the actual cell count.
-dwg_status mc_prepare(const float* P, const float* N, const float* area, const float* delta, int64_t n,
-                      const dwg_kernel_params& kp, const McParams& mp, void* ws, size_t ws_bytes, hipStream_t st,
-                      McWork* w, EvalState* es) {
-  Carver c(ws);
-  carve_mc_grid(c, n, mp, w);
-  int64_t C = 0;
-  DWG_PROPAGATE(mc_cells(P, n, mp, *w, &C, st));
-  const size_t need = mc_bytes(n, kp, mp, C);
-  if (ws_bytes < need) {
-    set_error("workspace too small for %lld grid cells: %zu bytes given, %zu needed", (long long)C, ws_bytes, need);
-    return DWG_E_WORKSPACE;
-  }
-  DWG_CHECK(12 * C < (int64_t(1) << 31), "too many grid cells (%lld)", (long long)C);
-  carve_mc_faces(c, n, C, mp.k, w);
-  int64_t m = 0;
-  DWG_PROPAGATE(mc_corners(mp, *w, &m, st));
-  if (mp.iso_points) DWG_PROPAGATE(mc_append_points(P, n, *w, st));
-  DWG_PROPAGATE(knn_grid(P, n, w->knn, st));
-  DWG_PROPAGATE(mc_clear(*w, st));
-  return eval_prepare(P, N, area, delta, n, w->pos, w->ld, kp, false, static_cast<char*>(ws) + c.used, st, es);
-}
-
-// w at the corners (and at the points when w_bar is taken over them) and w_bar.
-dwg_status mc_field(const dwg_kernel_params& kp, const McParams& mp, const McWork& w, const EvalState& es,
-                    hipStream_t st) {
-  DWG_PROPAGATE(eval_run(w.pos, w.ld, kp, false, es, st));
-  if (!mp.iso_points) return launch_combine(w.ld, kp, false, w.wc, nullptr, w.iso, es.wk, st);
-  DWG_PROPAGATE(launch_combine(w.ld, kp, false, w.wc, nullptr, nullptr, es.wk, st));
-  return mc_point_iso(w, w.wc + w.m, w.n, st);
-}
-
-}  // namespace
-
-extern "C" {
 
 size_t dwg_mc_workspace_bytes(int64_t n, const dwg_kernel_params* kp, const dwg_mc_params* mcp, int64_t cells) {
   McParams mp;
@@ -470,9 +462,6 @@ dwg_status dwg_level_set(const float* P, const float* N, const float* area, cons
   return DWG_OK;
 }
 
-}  // extern "C"
-
-extern "C" {
 
 dwg_status dwg_octree(const float* P, int64_t n, int leaf, int32_t* perm, int32_t* nodes, int64_t cap,
                       int64_t* count, void* ws, size_t ws_bytes, void* stream) {

@@ -24,6 +24,7 @@
 #include <cmath>
 
 #include "dwg_internal.h"
+#include "dwg_morton.h"
 
 #define DWG_PROPAGATE_INT(expr) \
   do {                          \
@@ -34,49 +35,20 @@
 namespace dwg {
 namespace {
 
-constexpr int kDepth21 = 21;
+using morton::compact21;
 
-__device__ __forceinline__ uint64_t spread21(uint64_t x) {
-  x &= 0x1fffffull;
-  x = (x | (x << 32)) & 0x1f00000000ffffull;
-  x = (x | (x << 16)) & 0x1f0000ff0000ffull;
-  x = (x | (x << 8)) & 0x100f00f00f00f00full;
-  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
-  x = (x | (x << 2)) & 0x1249249249249249ull;
-  return x;
-}
-
-__device__ __forceinline__ int compact21(uint64_t x) {
-  x &= 0x1249249249249249ull;
-  x = (x ^ (x >> 2)) & 0x10c30c30c30c30c3ull;
-  x = (x ^ (x >> 4)) & 0x100f00f00f00f00full;
-  x = (x ^ (x >> 8)) & 0x1f0000ff0000ffull;
-  x = (x ^ (x >> 16)) & 0x1f00000000ffffull;
-  x = (x ^ (x >> 32)) & 0x1fffffull;
-  return (int)x;
-}
-
-__device__ __forceinline__ uint64_t morton3(int x, int y, int z) {
-  return (spread21((uint64_t)x) << 2) | (spread21((uint64_t)y) << 1) | spread21((uint64_t)z);
-}
+__device__ __forceinline__ uint64_t morton3(int x, int y, int z) { return morton::code3(x, y, z); }
 
 unsigned grid_of(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 256), 16384)); }
 
 // Cell code of every point at `depth` (from the level-21 octree cell).
 __global__ void k_mc_point_keys(const float* __restrict__ P, int64_t n, const double* __restrict__ frame, int depth,
                                 uint64_t* __restrict__ key, int32_t* __restrict__ val) {
-  const double sc = frame[3];
+  const int sh = morton::kDepth - depth;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     int c[3];
-    for (int d = 0; d < 3; ++d) {
-      double f = 0.0;
-      if (sc > 0.0) {
-        f = floor(__dmul_rn(__dsub_rn((double)P[d * n + i], frame[d]), sc));
-        f = f < 0.0 ? 0.0 : (f > 2097151.0 ? 2097151.0 : f);
-      }
-      c[d] = (int)f >> (kDepth21 - depth);
-    }
-    key[i] = morton3(c[0], c[1], c[2]);
+    morton::cell21(P, n, i, frame, c);
+    key[i] = morton3(c[0] >> sh, c[1] >> sh, c[2] >> sh);
     val[i] = 0;
   }
 }

@@ -37,14 +37,14 @@
 #include <cmath>
 
 #include "dwg_internal.h"
+#include "dwg_morton.h"
 #include "dwg_pair.h"
 
 namespace dwg {
 namespace {
 
 using namespace pairk;
-
-constexpr int kDepth = 21;
+using morton::kDepth;
 constexpr int kSortTile = 2048;  // elements per block of the radix sort (256 threads x 8 rounds)
 constexpr int kScanTile = 2048;  // elements per block of the FP64 scans (256 threads x 8)
 constexpr int kChunk = 256;      // sources per work item of the radius pass
@@ -57,16 +57,6 @@ __device__ __forceinline__ int64_t node_count(const int32_t* total_p, int64_t ca
 
 unsigned grid_cap(int64_t n, int64_t cap = 16384) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 256), cap));
-}
-
-__device__ __forceinline__ uint64_t spread21(uint64_t x) {
-  x &= 0x1fffffull;
-  x = (x | (x << 32)) & 0x1f00000000ffffull;
-  x = (x | (x << 16)) & 0x1f0000ff0000ffull;
-  x = (x | (x << 8)) & 0x100f00f00f00f00full;
-  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
-  x = (x | (x << 2)) & 0x1249249249249249ull;
-  return x;
 }
 
 // Number of levels 1..D at which codes a and b share their cell (D when equal).
@@ -110,18 +100,10 @@ __global__ void k_tree_frame(const float* __restrict__ box, double* __restrict__
 
 __global__ void k_tree_keys(const float* __restrict__ P, int64_t n, const double* __restrict__ frame,
                             uint64_t* __restrict__ key, int32_t* __restrict__ val) {
-  const double sc = frame[3];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    uint64_t c[3];
-    for (int d = 0; d < 3; ++d) {
-      double f = 0.0;
-      if (sc > 0.0) {
-        f = floor(__dmul_rn(__dsub_rn((double)P[d * n + i], frame[d]), sc));
-        f = f < 0.0 ? 0.0 : (f > 2097151.0 ? 2097151.0 : f);
-      }
-      c[d] = (uint64_t)f;
-    }
-    key[i] = (spread21(c[0]) << 2) | (spread21(c[1]) << 1) | spread21(c[2]);
+    int c[3];
+    morton::cell21(P, n, i, frame, c);
+    key[i] = morton::code3(c[0], c[1], c[2]);
     val[i] = (int32_t)i;
   }
 }
