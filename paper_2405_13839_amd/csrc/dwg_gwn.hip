@@ -210,11 +210,6 @@ __global__ __launch_bounds__(kBlock) void k_query_box(const float* __restrict__ 
   }
 }
 
-__global__ void k_iota(int32_t* __restrict__ p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = (int32_t)i;
-}
-
 // Sum of `split` partials of accumulator `a` for sorted query i, in split order.
 __device__ __forceinline__ float combine(const float* part, int split, int64_t mpad, int na, int a, int64_t i,
                                          bool kahan) {
