@@ -4,6 +4,7 @@ the normals, in all-pairs and octree mode. Inputs come from the seeded generator
 oracle only."""
 import numpy as np
 import pytest
+import torch
 
 import oracle
 from oracle import mc
@@ -71,3 +72,21 @@ def test_mc_iterate_holds_the_sphere():
                                max_iters=10)
     ang = angle_deg(host(Nt), s.N_true)
     assert np.mean(ang < 90) > 0.999 and np.median(ang) < 8.0 and 0.4 < stats[-1, 0].item() < 0.6
+
+
+def test_mc_update_is_deterministic():
+    """The fixed-point scatter makes the level-set update bitwise reproducible."""
+    dwg = _dwg()
+    c = synth.torus_ellipsoids(30_000, seed=4243)
+    rng = np.random.default_rng(4)
+    N = cuda(unit_rows(rng, c.n))
+    P, a = cuda(c.P), cuda(c.area)
+    d = cuda(oracle.anchor_delta(c.P).astype(np.float32))
+    prm = dwg.Params(lam=10.0, beta=2.3)
+    N1, N2 = N.clone(), N.clone()
+    s1 = dwg.iterate_mc(P, a, d, N1, prm, depth=6, max_iters=3, fixed_iters=True)[1]
+    s2 = dwg.iterate_mc(P, a, d, N2, prm, depth=6, max_iters=3, fixed_iters=True)[1]
+    assert torch.equal(N1, N2) and torch.equal(s1[:, :3], s2[:, :3])
+    t1, i1 = dwg.level_set(P, N1, a, d, prm, depth=6)
+    t2, i2 = dwg.level_set(P, N1, a, d, prm, depth=6)
+    assert torch.equal(t1, t2) and i1 == i2
