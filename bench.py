@@ -204,17 +204,32 @@ def main() -> int:
         Nh = rng.standard_normal((3, n))
         Nh /= np.linalg.norm(Nh, axis=0)
         dh = np.full(n, 0.02)
-        oracle.num_threads()
+        threads = oracle.num_threads()
         t2 = time.perf_counter()
         oracle.gwn(cloud.P, Nh, cloud.area, dh, cloud.P[:, sel], lam=args.lam)
         ct = time.perf_counter() - t2
+        one = sel[: max(1, len(sel) // 64)]
+        oracle.set_num_threads(1)
+        t3 = time.perf_counter()
+        oracle.gwn(cloud.P, Nh, cloud.area, dh, cloud.P[:, one], lam=args.lam)
+        ct1 = time.perf_counter() - t3
+        oracle.set_num_threads(threads)
+        cpu_model = ""
+        try:
+            cpu_model = next(ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name"))
+        except (OSError, StopIteration):
+            pass
         result["cpu_baseline"] = {
             "value": len(sel) * n / ct,
             "unit": "pair-interactions/s",
-            "cores": oracle.num_threads(),
+            "cores": threads,
             "kind": "oracle",
             "sample": f"{len(sel)} random queries x {n} sources, same screened kernel, FP64 "
                       f"({ct:.1f} s); per-iteration time extrapolates to {n * n / (len(sel) * n / ct):.0f} s",
+            "one_thread_value": len(one) * n / ct1,
+            "one_thread_sample": f"{len(one)} queries x {n} sources on 1 thread ({ct1:.1f} s)",
+            "nproc": os.cpu_count(),
+            "cpu_model": cpu_model,
         }
     print(json.dumps(result), flush=True)
     return 0

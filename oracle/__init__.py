@@ -61,6 +61,7 @@ def _load():
         lib.orc_splitmix64.restype = ctypes.c_uint64
         lib.orc_random_normals.argtypes = [ctypes.c_uint64, i64, dp]
         lib.orc_num_threads.restype = ctypes.c_int
+        lib.orc_set_num_threads.argtypes = [ctypes.c_int]
         lp = ctypes.POINTER(ctypes.c_int64)
         lib.orc_octree.argtypes = [dp, i64, ctypes.c_int, lp, lp, i64]
         lib.orc_octree.restype = i64
@@ -84,6 +85,11 @@ def _p(a, ct=ctypes.c_double):
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(t: int) -> None:
+    """Threads of the oracle's later OpenMP loops (results do not depend on it)."""
+    _load().orc_set_num_threads(int(t))
 
 
 def gwn(P, N, area, delta, Q, lam=0.0, eps=0.0, grad=True):

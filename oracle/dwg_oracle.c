@@ -359,3 +359,13 @@ int orc_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Sets the number of OpenMP threads of later parallel loops (no effect without OpenMP). */
+void orc_set_num_threads(int t) {
+#ifdef _OPENMP
+  extern void omp_set_num_threads(int);
+  if (t >= 1) omp_set_num_threads(t);
+#else
+  (void)t;
+#endif
+}
