@@ -7,7 +7,8 @@
  *
  * Conventions shared by every call
  *  - Point arrays are planar ("SoA") float32 device arrays of shape [3][n]: x at [0,n),
- *    y at [n,2n), z at [2n,3n) -- a contiguous (3, n) torch tensor.
+ *    y at [n,2n), z at [2n,3n) -- a contiguous (3, n) torch tensor. Point counts are below
+ *    2^31 (int32 point indices; some calls state tighter limits).
  *  - Every pointer argument is a DEVICE pointer to caller-owned memory unless it says
  *    "host". The library never allocates, frees or keeps caller memory.
  *  - Scratch memory comes only from the caller's workspace `ws` of `ws_bytes` bytes
@@ -97,8 +98,8 @@ size_t dwg_workspace_bytes(int64_t n_src, int64_t n_qry, const dwg_kernel_params
  *   P, N: sources and their normals [3][n]; area: a_j [n]; delta: per-source radius [n]
  *   or NULL (= 0); Q: queries [3][m]; w: output [m]; wmean: output, one double = the FP64
  *   mean of w, or NULL.
- *   Errors: DWG_E_INVALID (NULL P/N/area/Q/w, n < 1, m < 1, lambda or eps negative or not
- *   finite, nonzero reserved), DWG_E_WORKSPACE, DWG_E_DEVICE.
+ *   Errors: DWG_E_INVALID (NULL P/N/area/Q/w, n or m outside [1, 2^31), lambda or eps
+ *   negative or not finite, nonzero reserved), DWG_E_WORKSPACE, DWG_E_DEVICE.
  */
 dwg_status dwg_gwn_eval(const float* P, const float* N, const float* area, const float* delta,
                         int64_t n, const float* Q, int64_t m, const dwg_kernel_params* kp,

@@ -156,7 +156,7 @@ dwg_status gwn_common(const float* P, const float* N, const float* area, const f
                       void* stream) {
   DWG_CHECK(P && N && area && Q, "P, N, area and Q must not be NULL");
   DWG_CHECK(n >= 1 && m >= 1, "n and m must be >= 1 (got n=%lld, m=%lld)", (long long)n, (long long)m);
-  DWG_CHECK(n < (int64_t(1) << 40) && m < (int64_t(1) << 40), "n, m too large");
+  DWG_CHECK(n < (int64_t(1) << 31) && m < (int64_t(1) << 31), "n and m must be < 2^31 (int32 point indices)");
   DWG_CHECK(grad ? (g != nullptr) : (w != nullptr), grad ? "grad must not be NULL" : "w must not be NULL");
   DWG_PROPAGATE(check_kp(kpp));
   const dwg_kernel_params kp = kpp ? *kpp : kDefaultKp;
@@ -254,7 +254,7 @@ const char* dwg_status_string(int s) {
 const char* dwg_last_error(void) { return g_err; }
 
 size_t dwg_workspace_bytes(int64_t n_src, int64_t n_qry, const dwg_kernel_params* kp) {
-  if (n_src < 1 || n_qry < 1 || n_src >= (int64_t(1) << 40) || n_qry >= (int64_t(1) << 40)) return 0;
+  if (n_src < 1 || n_qry < 1 || n_src >= (int64_t(1) << 31) || n_qry >= (int64_t(1) << 31)) return 0;
   if (check_kp(kp) != DWG_OK) return 0;
   const dwg_kernel_params k = kp ? *kp : kDefaultKp;
   size_t a = gwn_bytes(n_src, n_qry, k);
@@ -282,7 +282,7 @@ dwg_status dwg_iterate(const float* P, const float* area, const float* delta, in
                        void* stream) {
   if (iters_done) *iters_done = 0;
   DWG_CHECK(P && area && N_inout && ip, "P, area, N_inout and ip must not be NULL");
-  DWG_CHECK(n >= 1 && n < (int64_t(1) << 40), "n must be >= 1 (got %lld)", (long long)n);
+  DWG_CHECK(n >= 1 && n < (int64_t(1) << 31), "n must be in [1, 2^31) (got %lld)", (long long)n);
   DWG_CHECK(ip->max_iters >= 1, "max_iters must be >= 1");
   DWG_CHECK(ip->fixed_iters == 0 || ip->fixed_iters == 1, "fixed_iters must be 0 or 1");
   DWG_CHECK(std::isfinite(ip->eps_deg) && ip->eps_deg >= 0.0, "eps_deg must be finite and >= 0");
@@ -496,7 +496,7 @@ dwg_status dwg_init_normals(dwg_init_kind kind, uint64_t seed, const float* P, i
   DWG_CHECK(kind == DWG_INIT_RANDOM || kind == DWG_INIT_MLP || kind == DWG_INIT_PCA || kind == DWG_INIT_GAUSS,
             "unknown init kind %d", (int)kind);
   DWG_CHECK(N_out, "N_out must not be NULL");
-  DWG_CHECK(n >= 1 && n < (int64_t(1) << 40), "n must be >= 1");
+  DWG_CHECK(n >= 1 && n < (int64_t(1) << 31), "n must be in [1, 2^31)");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (kind == DWG_INIT_RANDOM) {
     DWG_PROPAGATE(check_device());

@@ -61,6 +61,8 @@ def test_invalid_arguments_rejected_before_device():
     assert _call_grad(g=None) == dwg.DWG_E_INVALID
     assert _call_grad(n=0) == dwg.DWG_E_INVALID
     assert _call_grad(m=-3) == dwg.DWG_E_INVALID
+    assert _call_grad(n=1 << 31) == dwg.DWG_E_INVALID  # int32 point indices
+    assert _call_grad(m=1 << 31) == dwg.DWG_E_INVALID
     for bad in [dwg.Params(lam=-1), dwg.Params(lam=float("nan")), dwg.Params(eps=-1e-3), dwg.Params(split=65),
                 dwg.Params(beta=0.5), dwg.Params(beta=float("inf")), dwg.Params(beta=2.3, leaf=-1),
                 dwg.Params(beta=2.3, leaf=2000)]:
