@@ -132,14 +132,14 @@ dwg_status eval_prepare(const float* P, const float* N, const float* area, const
   es->tree = tree_mode(kp);
   if (!es->tree) {
     carve_gwn(c, n, m, choose_split(n, m, kp.split), same, &es->wk);
-    DWG_PROPAGATE(launch_order(P, n, delta, kp.eps, Q, m, same, es->wk, st));
-    return launch_stage(P, N, area, delta, n, kp.eps, es->wk, st);
+    DWG_PROPAGATE(launch_order(P, n, delta, kp.eps, position_scale(kp), Q, m, same, es->wk, st));
+    return launch_stage(P, N, area, delta, n, kp.eps, position_scale(kp), es->wk, st);
   }
   carve_gwn(c, n, m, 1, same, &es->wk);
   carve_tree(c, n, tree_leaf(kp), kp.tree_beta, &es->tw);
   DWG_PROPAGATE(tree_build(P, area, delta, n, kp.eps, es->tw, es->wk.perm_s, st));
   if (!same) DWG_PROPAGATE(spatial_sort(Q, m, nullptr, 0.0f, es->wk.sort, es->wk.perm_q, st));
-  return launch_stage(P, N, area, delta, n, kp.eps, es->wk, st);
+  return launch_stage(P, N, area, delta, n, kp.eps, position_scale(kp), es->wk, st);
 }
 
 // w (and grad) at the sorted queries into the per-query partials.

@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kBlock) void k_gwn(const float* __restrict__ Q, int
                                                  const float4* __restrict__ src, int64_t ntiles,
                                                  int64_t nfull, int64_t tiles_per_split,
                                                  const float4* __restrict__ tbox,
-                                                 const float4* __restrict__ qbox, Scr sk,
+                                                 const float4* __restrict__ qbox, Scr sk, float kappa,
                                                  float* __restrict__ part, int64_t mpad) {
   constexpr int NA = GRAD ? kNAcc : 1;
   __shared__ float4 sa[kTile];
@@ -66,9 +66,9 @@ __global__ __launch_bounds__(kBlock) void k_gwn(const float* __restrict__ Q, int
     int64_t qi = q0 + k * kBlock + tid;
     if (qi >= m) qi = m - 1;
     const int64_t o = qperm[qi];
-    qx[k] = Q[o];
-    qy[k] = Q[m + o];
-    qz[k] = Q[2 * m + o];
+    qx[k] = kappa * Q[o];
+    qy[k] = kappa * Q[m + o];
+    qz[k] = kappa * Q[2 * m + o];
   }
   const float4 qlo = qbox[2 * blockIdx.x], qhi = qbox[2 * blockIdx.x + 1];
   float sum[QPT][NA], cmp[QPT][NA];
@@ -123,11 +123,12 @@ __global__ __launch_bounds__(kBlock) void k_gwn(const float* __restrict__ Q, int
   }
 }
 
-// Stage the sources in spatial order: (p, 1/max(delta,eps)) and m = a n / (4 pi).
+// Stage the sources in spatial order: (kappa p, 1/(kappa max(delta,eps))) and m = a n / (4 pi)
+// (kappa = the position scale of the kernel, 1 when plain).
 // A NaN delta poisons the source's m so that the result is NaN as in the definition.
 __global__ void k_stage(const float* __restrict__ P, const float* __restrict__ N,
                         const float* __restrict__ A, const float* __restrict__ D, int64_t n,
-                        int64_t npad, float eps, const int32_t* __restrict__ perm,
+                        int64_t npad, float eps, float kappa, const int32_t* __restrict__ perm,
                         float4* __restrict__ src, float* __restrict__ kk) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= npad) return;
@@ -136,11 +137,11 @@ __global__ void k_stage(const float* __restrict__ P, const float* __restrict__ N
   if (j < n) {
     const int64_t o = perm[j];
     const float d = D ? D[o] : 0.0f;
-    const float fl = d > eps ? d : eps;
+    const float fl = kappa * (d > eps ? d : eps);
     const float id = fl > 0.0f ? 1.0f / fl : INFINITY;
     k = A[o] * kInv4Pi;
     if (d != d) k = NAN;
-    a = make_float4(P[o], P[n + o], P[2 * n + o], id);
+    a = make_float4(kappa * P[o], kappa * P[n + o], kappa * P[2 * n + o], id);
     b = make_float4(k * N[o], k * N[n + o], k * N[2 * n + o], 0.0f);
   }
   src[2 * j] = a;
@@ -177,9 +178,9 @@ __global__ __launch_bounds__(kTile) void k_tile_box(const float4* __restrict__ s
   }
 }
 
-// Box of each block of kQBlock sorted queries.
+// Box of each block of kQBlock sorted queries (scaled coordinates).
 __global__ __launch_bounds__(kBlock) void k_query_box(const float* __restrict__ Q, int64_t m,
-                                                      const int32_t* __restrict__ qperm,
+                                                      const int32_t* __restrict__ qperm, float kappa,
                                                       float4* __restrict__ qbox) {
   __shared__ float lds[6][kBlock];
   float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
@@ -187,7 +188,7 @@ __global__ __launch_bounds__(kBlock) void k_query_box(const float* __restrict__ 
     int64_t qi = (int64_t)blockIdx.x * kQBlock + k * kBlock + threadIdx.x;
     if (qi >= m) qi = m - 1;  // the kernel evaluates the clamped query there as well
     const int64_t o = qperm[qi];
-    const float x = Q[o], y = Q[m + o], z = Q[2 * m + o];
+    const float x = kappa * Q[o], y = kappa * Q[m + o], z = kappa * Q[2 * m + o];
     v[0] = fminf(v[0], x);
     v[1] = fminf(v[1], y);
     v[2] = fminf(v[2], z);
@@ -246,7 +247,10 @@ struct Scale {
   float ws, as, bs;
 };
 Scale scale_of(const dwg_kernel_params& kp) {
-  return kp.lambda > 0.0f ? Scale{1.0f / 3.0f, 1.0f, 1.0f / 3.0f} : Scale{1.0f, 3.0f, 1.0f};
+  if (!(kp.lambda > 0.0f)) return Scale{1.0f, 3.0f, 1.0f};
+  // screened sums in scaled coordinates: w' carries 1/kappa^2, A and B' carry 1/kappa^3
+  const double k = position_scale(kp);
+  return Scale{(float)(k * k / 3.0), (float)(k * k * k), (float)(k * k * k / 3.0)};
 }
 
 // Evaluation epilogue: combine splits; write w and grad at the query's original index;
@@ -448,14 +452,17 @@ __global__ void k_random_normals(uint64_t seed, int64_t n, float* __restrict__ N
 
 template <int QPT, bool GRAD, bool SCREENED, bool KAHAN>
 void launch_gwn_t(dim3 grid, hipStream_t st, const float* Q, int64_t m, const int32_t* qperm,
-                  const GwnWork& w, int64_t tps, float s) {
-  const Scr sk{3.0f * s, -s * 1.4426950408889634f, s * s};
+                  const GwnWork& w, int64_t tps, float kappa) {
   const int64_t nfull = w.n_src / kTile;  // tiles without padding
   hipLaunchKernelGGL((k_gwn<QPT, GRAD, SCREENED, KAHAN>), grid, dim3(kBlock), 0, st, Q, m, qperm, w.src,
-                     w.ntiles, nfull, tps, w.tbox, w.qbox, sk, w.part, w.mpad);
+                     w.ntiles, nfull, tps, w.tbox, w.qbox, kScaledScr, kappa, w.part, w.mpad);
 }
 
 }  // namespace
+
+float position_scale(const dwg_kernel_params& kp) {
+  return kp.lambda > 0.0f ? (float)(std::sqrt((double)kp.lambda) * 1.4426950408889634) : 1.0f;
+}
 
 int choose_split(int64_t n_src, int64_t n_qry, int requested) {
   const int64_t ntiles = cdiv(n_src, kTile);
@@ -495,17 +502,17 @@ size_t carve_gwn(Carver& c, int64_t n_src, int64_t n_qry, int split, bool same, 
 }
 
 dwg_status launch_stage(const float* P, const float* N, const float* area, const float* delta,
-                        int64_t n, float eps, const GwnWork& w, hipStream_t stream) {
+                        int64_t n, float eps, float kappa, const GwnWork& w, hipStream_t stream) {
   hipLaunchKernelGGL(k_stage, dim3((unsigned)cdiv(w.npad, 256)), dim3(256), 0, stream, P, N, area,
-                     delta, n, w.npad, eps, w.perm_s, w.src, w.kk);
+                     delta, n, w.npad, eps, kappa, w.perm_s, w.src, w.kk);
   DWG_TRY_LAUNCH();
   hipLaunchKernelGGL(k_tile_box, dim3((unsigned)w.ntiles), dim3(kTile), 0, stream, w.src, n, w.tbox);
   DWG_TRY_LAUNCH();
   return DWG_OK;
 }
 
-dwg_status launch_order(const float* P, int64_t n, const float* delta, float eps, const float* Q, int64_t m,
-                        bool same, const GwnWork& w, hipStream_t stream) {
+dwg_status launch_order(const float* P, int64_t n, const float* delta, float eps, float kappa, const float* Q,
+                        int64_t m, bool same, const GwnWork& w, hipStream_t stream) {
   dwg_status s = spatial_sort(P, n, delta, eps, w.sort, w.perm_s, stream);
   if (s != DWG_OK) return s;
   if (!same) {
@@ -513,7 +520,7 @@ dwg_status launch_order(const float* P, int64_t n, const float* delta, float eps
     if (s != DWG_OK) return s;
   }
   hipLaunchKernelGGL(k_query_box, dim3((unsigned)(w.mpad / kQBlock)), dim3(kBlock), 0, stream, Q, m, w.perm_q,
-                     w.qbox);
+                     kappa, w.qbox);
   DWG_TRY_LAUNCH();
   return DWG_OK;
 }
@@ -525,9 +532,9 @@ dwg_status launch_gwn(const float* Q, int64_t m, const dwg_kernel_params& kp, bo
   dim3 grid((unsigned)qblocks, (unsigned)w.split);
   const bool scr = kp.lambda > 0.0f;
   const bool kah = kp.compensated != 0;
-  const float s = sqrtf(kp.lambda);
+  const float kappa = position_scale(kp);
 #define DWG_GWN_CASE(G, S, K) \
-  if (grad == G && scr == S && kah == K) launch_gwn_t<kQpt, G, S, K>(grid, stream, Q, m, w.perm_q, w, tps, s);
+  if (grad == G && scr == S && kah == K) launch_gwn_t<kQpt, G, S, K>(grid, stream, Q, m, w.perm_q, w, tps, kappa);
   DWG_GWN_CASE(true, false, true)
   DWG_GWN_CASE(true, false, false)
   DWG_GWN_CASE(true, true, true)

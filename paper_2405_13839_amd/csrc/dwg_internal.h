@@ -51,6 +51,10 @@ struct Carver {
   }
 };
 
+// Scale of the staged positions: s log2(e) for the screened kernel (s = sqrt(lambda)), 1 for
+// the plain one (see dwg_pair.h).
+float position_scale(const dwg_kernel_params& kp);
+
 // Split count for the all-pairs kernels.
 int choose_split(int64_t n_src, int64_t n_qry, int requested);
 
@@ -253,10 +257,10 @@ dwg_status mlp_forward(const float* params, const float* X, int64_t B, float* Y,
                        hipStream_t stream);
 
 // Launchers (all enqueue on `stream`; return DWG_OK or DWG_E_DEVICE).
-dwg_status launch_order(const float* P, int64_t n, const float* delta, float eps, const float* Q, int64_t m,
-                        bool same, const GwnWork& w, hipStream_t stream);
+dwg_status launch_order(const float* P, int64_t n, const float* delta, float eps, float kappa, const float* Q,
+                        int64_t m, bool same, const GwnWork& w, hipStream_t stream);
 dwg_status launch_stage(const float* P, const float* N, const float* area, const float* delta,
-                        int64_t n, float eps, const GwnWork& w, hipStream_t stream);
+                        int64_t n, float eps, float kappa, const GwnWork& w, hipStream_t stream);
 dwg_status launch_gwn(const float* Q, int64_t m, const dwg_kernel_params& kp, bool grad,
                       const GwnWork& w, hipStream_t stream);
 dwg_status launch_combine(int64_t m, const dwg_kernel_params& kp, bool grad, float* wout,

@@ -27,12 +27,15 @@ __device__ __forceinline__ float min3_nonneg(float a, float b, float c) {
   return __uint_as_float(min(min(x, y), z));
 }
 
-// Per-pair constants of the screened kernel.
+// Per-pair constants of the screened kernel. The screened kernel works in scaled coordinates
+// x' = kappa x with kappa = s log2(e) (the sources are staged and the queries loaded that
+// way), so that e^{-s r} = 2^{-r'} needs no multiply; then s r = ln(2) r' and the s^2 term
+// becomes ln(2)^2 in units of 1/r'^2. The epilogue multiplies the sums by the powers of kappa.
 struct Scr {
-  float s3;           // 3 s
-  float neg_s_log2e;  // -s log2(e)
-  float s2;           // s^2
+  float s3;  // 3 s / kappa = 3 ln 2
+  float s2;  // s^2 / kappa^2 = (ln 2)^2
 };
+constexpr Scr kScaledScr{2.0794415416798359f, 0.48045301391820144f};
 
 // One (query, source) pair of the plain kernel (Eq. 2-3 with the modified Poisson kernel).
 //   ip = 1/rho = min(1/r, 1/max(delta,eps)), and 0 when r == 0 (pair skipped).
@@ -69,7 +72,8 @@ __device__ __forceinline__ void pair_plain(const float4 a, const float4 b, float
   pair_plain_d<GRAD, FAR>(a.x - qx, a.y - qy, a.z - qz, a.w, b, acc);
 }
 
-// One pair of the screened kernel (Eq. 5): E = e^{-s r}, o3 = 3 (1 + s r), f = E ip^3.
+// One pair of the screened kernel (Eq. 5), in the scaled coordinates above (r is r'):
+// E = e^{-s r} = 2^{-r'}, o3 = 3 (1 + s r), f = E ip^3.
 //   w' += c f o3            (= 3 w)
 //   B' += f o3 m            (= 3 B with B = sum phi ip^3 m)
 //   A  += c f (o3 ip^2 [rho == r] + s^2) d
@@ -83,7 +87,7 @@ __device__ __forceinline__ void pair_screened_d(float dx, float dy, float dz, fl
   const float ip2 = ip * ip;
   const float ip3 = ip2 * ip;
   const float r = r2 * ir;
-  const float E = exp2_hw(r * k.neg_s_log2e);
+  const float E = exp2_hw(-r);
   const float o3 = fmaf(k.s3, r, 3.0f);
   const float f = E * ip3;
   const float c = fmaf(dz, b.z, fmaf(dy, b.y, dx * b.x));

@@ -32,8 +32,8 @@
 // wave descends (i + 1) when any active lane must open node i, sums a leaf's sources for the
 // lanes that opened it, and otherwise jumps to skip. Every query thus sees exactly the
 // per-query decisions of the paper's depth-first traversal; node loads are wave-uniform.
-// The FP64 criterion |q - c.m|^2 > crit^2 decides; the far dipole and the leaf pairs use the
-// FP32 pair arithmetic of the all-pairs kernel.
+// The FP64 criterion |q - c.m|^2 > crit^2 decides (unscaled); the far dipole and the leaf
+// pairs use the FP32 pair arithmetic of the all-pairs kernel in its scaled coordinates.
 #include <cmath>
 
 #include "dwg_internal.h"
@@ -482,12 +482,14 @@ __global__ __launch_bounds__(256) void k_tree_eval(const float* __restrict__ Q, 
                                                    const double4* __restrict__ geo, const float4* __restrict__ mom,
                                                    const int32_t* __restrict__ total_p, int64_t cap,
                                                    const float4* __restrict__ src, int64_t n_src, Scr sk,
-                                                   float* __restrict__ part, int64_t mpad) {
+                                                   float kappa, float* __restrict__ part, int64_t mpad) {
   constexpr int NA = GRAD ? kNAcc : 1;
   const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t o = qperm[qi < m ? qi : m - 1];
-  const float qx = Q[o], qy = Q[m + o], qz = Q[2 * m + o];
-  const double dqx = qx, dqy = qy, dqz = qz;
+  const float ux = Q[o], uy = Q[m + o], uz = Q[2 * m + o];
+  const double dqx = ux, dqy = uy, dqz = uz;  // the opening test runs in unscaled FP64
+  const float qx = kappa * ux, qy = kappa * uy, qz = kappa * uz;  // the pairs in the staged (scaled) units
+  const double dk = kappa;
   float sum[NA], cmp[NA], acc[NA];
 #pragma unroll
   for (int a = 0; a < NA; ++a) sum[a] = cmp[a] = acc[a] = 0.0f;
@@ -509,10 +511,11 @@ __global__ __launch_bounds__(256) void k_tree_eval(const float* __restrict__ Q, 
       const double dx = g.x - dqx, dy = g.y - dqy, dz = g.z - dqz;
       const double d2 = dx * dx + dy * dy + dz * dz;
       if (d2 > g.w) {
+        const float fx = (float)(dk * dx), fy = (float)(dk * dy), fz = (float)(dk * dz);
         if (SCREENED)
-          pair_screened_d<GRAD, true>((float)dx, (float)dy, (float)dz, 0.0f, mm, sk, acc);
+          pair_screened_d<GRAD, true>(fx, fy, fz, 0.0f, mm, sk, acc);
         else
-          pair_plain_d<GRAD, true>((float)dx, (float)dy, (float)dz, 0.0f, mm, acc);
+          pair_plain_d<GRAD, true>(fx, fy, fz, 0.0f, mm, acc);
         skip_to = nskip;
       } else if (nd.w >> 8) {
         direct = true;
@@ -591,11 +594,11 @@ dwg_status scan_f64(const float4* src, int64_t n, const TreeWork& t, hipStream_t
 }
 
 template <bool GRAD, bool SCREENED, bool KAHAN>
-void launch_eval_t(const float* Q, int64_t m, const int32_t* qperm, const GwnWork& w, const TreeWork& t, float s,
-                   hipStream_t st) {
-  const Scr sk{3.0f * s, -s * 1.4426950408889634f, s * s};
+void launch_eval_t(const float* Q, int64_t m, const int32_t* qperm, const GwnWork& w, const TreeWork& t,
+                   float kappa, hipStream_t st) {
   hipLaunchKernelGGL((k_tree_eval<GRAD, SCREENED, KAHAN>), dim3((unsigned)(w.mpad / 256)), dim3(256), 0, st, Q, m,
-                     qperm, t.node, t.geo, t.mom, t.off + t.n, t.cap, w.src, t.n, sk, w.part, w.mpad);
+                     qperm, t.node, t.geo, t.mom, t.off + t.n, t.cap, w.src, t.n, kScaledScr, kappa, w.part,
+                     w.mpad);
 }
 
 }  // namespace
@@ -722,9 +725,9 @@ dwg_status tree_eval(const float* Q, int64_t m, const dwg_kernel_params& kp, boo
                      const TreeWork& t, hipStream_t st) {
   const bool scr = kp.lambda > 0.0f;
   const bool kah = kp.compensated != 0;
-  const float s = sqrtf(kp.lambda);
+  const float kappa = position_scale(kp);
 #define DWG_TREE_CASE(G, S, K) \
-  if (grad == G && scr == S && kah == K) launch_eval_t<G, S, K>(Q, m, w.perm_q, w, t, s, st);
+  if (grad == G && scr == S && kah == K) launch_eval_t<G, S, K>(Q, m, w.perm_q, w, t, kappa, st);
   DWG_TREE_CASE(true, false, true)
   DWG_TREE_CASE(true, false, false)
   DWG_TREE_CASE(true, true, true)
