@@ -10,7 +10,7 @@ import torch
 
 import oracle
 from paper_2405_13839_amd import synth
-from tests.helpers import TOL_G, TOL_W, cuda, e_g, e_w, host, knn_radius, unit_rows
+from tests.helpers import TOL_G, TOL_W, cuda, e_g, e_w, host, unit_rows
 
 pytestmark = pytest.mark.gpu
 
@@ -134,15 +134,16 @@ def test_nan_input_propagates():
 
 
 def test_gwn_grad_full_size_sampled():
-    """The bench configuration: 1M points (torus + 2 ellipsoids), screened lambda = 10, radius
-    2 x mean 10-NN, the split and spatial order the library picks; 200 sampled queries are
-    recomputed by the oracle one by one."""
+    """The bench configuration: 1M points (torus + 2 ellipsoids), screened lambda = 10, the
+    anchor radius (mean distance to 10 of 4096 anchors, computed by the oracle), the split and
+    spatial order the library picks; 200 sampled queries are recomputed by the oracle one by
+    one."""
     dwg = _dwg()
     c = synth.torus_ellipsoids(1_000_000, seed=102)
     rng = np.random.default_rng(11)
     N = unit_rows(rng, c.n)
     Pc = cuda(c.P)
-    d = knn_radius(c.P)
+    d = oracle.anchor_delta(c.P, 10, 4096, 1.0).astype(np.float32)
     w, g = dwg.gwn(Pc, cuda(N), cuda(c.area), cuda(d), Pc, dwg.Params(lam=10.0))
     sel = rng.choice(c.n, 200, replace=False)
     w_ref, g_ref, flag = oracle.gwn(c.P, N, c.area, d, c.P[:, sel], lam=10.0)
