@@ -5,8 +5,9 @@
     python -m paper_2405_13839_amd.profiling mc   --n 1000000 --lam 10 --reps 5
     python -m paper_2405_13839_amd.profiling copy --mib 1024 --reps 3
 
-`gwn` launches the all-pairs kernel through dwg_gwn_grad on the C3 workload shape; `tree`
-runs dwg_iterate in octree mode (beta 2.3, anchor radius, fixed iterations) on it; `mc` runs
+`gwn` launches the all-pairs kernel through dwg_gwn_grad on the C3 workload shape (anchor
+radius: mean distance to 10 of 4096 anchors, random normals); `iterate` runs dwg_iterate
+with fixed iterations on it; `tree` the same in octree mode (beta 2.3); `mc` runs
 dwg_iterate_mc (the level-set update, depth 8, octree evaluation) on it; `copy`
 runs a plain device-to-device copy of a known size, used to calibrate the FETCH_SIZE /
 WRITE_SIZE counters (bytes the counters report per byte actually moved).
@@ -44,10 +45,7 @@ def main(argv=None) -> int:
     a = torch.from_numpy(c.area).to(dev)
     prm = dwg.Params(lam=args.lam, beta=2.3 if args.what in ("tree", "mc") else 0.0)
     ws = dwg.workspace(c.n, c.n, dev, prm)
-    if args.what in ("tree", "mc"):
-        d = dwg.delta_anchor_mean(P, 10, 4096, 1.0, ws=ws)
-    else:
-        d = dwg.delta_knn_mean(P, 10, 2.0, ws=ws)
+    d = dwg.delta_anchor_mean(P, 10, 4096, 1.0, ws=ws)  # the benchmark's kernel radius
     N = dwg.random_normals(c.n, 202, dev)
     if args.what == "gwn":
         for _ in range(args.reps):
