@@ -4,11 +4,14 @@
     python -m paper_2405_13839_amd.profiling tree --n 1000000 --lam 10 --reps 5
     python -m paper_2405_13839_amd.profiling mc   --n 1000000 --lam 10 --reps 5
     python -m paper_2405_13839_amd.profiling copy --mib 1024 --reps 3
+    python -m paper_2405_13839_amd.profiling mlp  --n 1000000 --reps 3
 
 `gwn` launches the all-pairs kernel through dwg_gwn_grad on the C3 workload shape (anchor
 radius: mean distance to 10 of 4096 anchors, random normals); `iterate` runs dwg_iterate
 with fixed iterations on it; `tree` the same in octree mode (beta 2.3); `mc` runs
-dwg_iterate_mc (the level-set update, depth 8, octree evaluation) on it; `copy`
+dwg_iterate_mc (the level-set update, depth 8, octree evaluation) on it; `mlp` computes
+the learned initial normals (anchor kNN, features, MLP inference) with the shipped weights;
+`copy`
 runs a plain device-to-device copy of a known size, used to calibrate the FETCH_SIZE /
 WRITE_SIZE counters (bytes the counters report per byte actually moved).
 """
@@ -20,7 +23,7 @@ import sys
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["gwn", "copy", "iterate", "tree", "mc"])
+    ap.add_argument("what", choices=["gwn", "copy", "iterate", "tree", "mc", "mlp"])
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--lam", type=float, default=10.0)
     ap.add_argument("--reps", type=int, default=2)
@@ -47,7 +50,16 @@ def main(argv=None) -> int:
     ws = dwg.workspace(c.n, c.n, dev, prm)
     d = dwg.delta_anchor_mean(P, 10, 4096, 1.0, ws=ws)  # the benchmark's kernel radius
     N = dwg.random_normals(c.n, 202, dev)
-    if args.what == "gwn":
+    if args.what == "mlp":
+        import os
+
+        from paper_2405_13839_amd import mlp_init
+
+        mlp = mlp_init.load_params(os.path.join(os.path.dirname(__file__), "weights", "mlp_init.safetensors"), dev)
+        for _ in range(args.reps):
+            dwg.mlp_normals(P, mlp, ws=ws)
+        torch.cuda.synchronize()
+    elif args.what == "gwn":
         for _ in range(args.reps):
             dwg.gwn(P, N, a, d, P, prm, ws=ws)
         torch.cuda.synchronize()
