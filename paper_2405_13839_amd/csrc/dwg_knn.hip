@@ -216,18 +216,35 @@ __device__ __forceinline__ bool less_pair(float d2, int i, float e2, int j) {
 // skip_mode: 0 none; 1 reference i == query i; 2 reference i / stride when i % stride == 0.
 // Queries q = 0..m-1 are points q0 + q of the planar array Q with leading dimension qld;
 // results go to idx[q][K], dist[q][K].
-template <int K>
+// SELF: the queries are the references themselves (m = their count, skip_mode 1): thread p
+// takes the p-th reference in cell order from `sorted` and writes the row of its original
+// index, so the lanes of a wavefront search neighbouring cells (same results, in another
+// order of work).
+template <int K, bool SELF>
 __global__ __launch_bounds__(256) void k_knn(const float* __restrict__ Q, int64_t qld, int64_t q0,
                                              int64_t m, const GridParams* __restrict__ gp,
                                              const int32_t* __restrict__ start,
                                              const float4* __restrict__ sorted, int skip_mode,
                                              int64_t stride, int32_t* __restrict__ idx,
                                              float* __restrict__ dist) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= m) return;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= m) return;
   const GridParams g = *gp;
-  const int64_t gq = q0 + q;
-  const float qx = Q[gq], qy = Q[qld + gq], qz = Q[2 * qld + gq];
+  int64_t q, gq;
+  float qx, qy, qz;
+  if (SELF) {
+    const float4 sp = sorted[p];
+    q = gq = __float_as_int(sp.w);
+    qx = sp.x;
+    qy = sp.y;
+    qz = sp.z;
+  } else {
+    q = p;
+    gq = q0 + q;
+    qx = Q[gq];
+    qy = Q[qld + gq];
+    qz = Q[2 * qld + gq];
+  }
   int skip = -1;
   if (skip_mode == 1) skip = (int)gq;
   if (skip_mode == 2 && (gq % stride) == 0) skip = (int)(gq / stride);
@@ -572,9 +589,13 @@ unsigned grid_for(int64_t n, int block = 256, int64_t cap = 65535) {
 
 template <int K>
 void launch_knn_k(int64_t m, hipStream_t st, const float* Q, int64_t qld, int64_t q0, const KnnWork& w,
-                  int skip_mode, int64_t stride, int32_t* idx, float* dist) {
-  hipLaunchKernelGGL(k_knn<K>, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, st, Q, qld, q0, m, w.gp, w.start,
-                     w.sorted, skip_mode, stride, idx, dist);
+                  int skip_mode, int64_t stride, bool self, int32_t* idx, float* dist) {
+  if (self)
+    hipLaunchKernelGGL((k_knn<K, true>), dim3((unsigned)cdiv(m, 256)), dim3(256), 0, st, Q, qld, q0, m, w.gp,
+                       w.start, w.sorted, skip_mode, stride, idx, dist);
+  else
+    hipLaunchKernelGGL((k_knn<K, false>), dim3((unsigned)cdiv(m, 256)), dim3(256), 0, st, Q, qld, q0, m, w.gp,
+                       w.start, w.sorted, skip_mode, stride, idx, dist);
 }
 
 dwg_status build_grid(const float* R, int64_t nr, const KnnWork& w, hipStream_t st) {
@@ -602,11 +623,12 @@ dwg_status build_grid(const float* R, int64_t nr, const KnnWork& w, hipStream_t 
   return DWG_OK;
 }
 
+// self: the queries are exactly the m references of the grid, q0 = 0, skip_mode 1.
 dwg_status knn_query(const float* Q, int64_t qld, int64_t q0, int64_t m, const KnnWork& w, int skip_mode,
-                     int64_t stride, int k, int32_t* idx, float* dist, hipStream_t st) {
+                     int64_t stride, int k, int32_t* idx, float* dist, hipStream_t st, bool self = false) {
   switch (k) {
 #define DWG_K(KK) \
-  case KK: launch_knn_k<KK>(m, st, Q, qld, q0, w, skip_mode, stride, idx, dist); break;
+  case KK: launch_knn_k<KK>(m, st, Q, qld, q0, w, skip_mode, stride, self, idx, dist); break;
     DWG_K(1) DWG_K(2) DWG_K(3) DWG_K(4) DWG_K(5) DWG_K(6) DWG_K(7) DWG_K(8)
     DWG_K(9) DWG_K(10) DWG_K(11) DWG_K(12) DWG_K(13) DWG_K(14) DWG_K(15) DWG_K(16)
 #undef DWG_K
@@ -678,7 +700,9 @@ dwg_status knn_run(const float* R, int64_t nr, const float* Q, int64_t m, int se
   carve_knn(c, nr, &w);
   dwg_status s = build_grid(R, nr, w, stream);
   if (s != DWG_OK) return s;
-  return knn_query(Q, m, 0, m, w, self_skip ? 1 : 0, 1, k, idx, dist, stream);
+  // queries that are the references themselves (same array, same count) run in cell order
+  const bool self = self_skip && Q == R && m == nr;
+  return knn_query(Q, m, 0, m, w, self_skip ? 1 : 0, 1, k, idx, dist, stream, self);
 }
 
 dwg_status delta_from_knn(const float* dist, int64_t n, int k, float scale, float* delta,

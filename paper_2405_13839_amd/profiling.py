@@ -5,12 +5,14 @@
     python -m paper_2405_13839_amd.profiling mc   --n 1000000 --lam 10 --reps 5
     python -m paper_2405_13839_amd.profiling copy --mib 1024 --reps 3
     python -m paper_2405_13839_amd.profiling mlp  --n 1000000 --reps 3
+    python -m paper_2405_13839_amd.profiling area --n 1000000 --reps 3
 
 `gwn` launches the all-pairs kernel through dwg_gwn_grad on the C3 workload shape (anchor
 radius: mean distance to 10 of 4096 anchors, random normals); `iterate` runs dwg_iterate
 with fixed iterations on it; `tree` the same in octree mode (beta 2.3); `mc` runs
 dwg_iterate_mc (the level-set update, depth 8, octree evaluation) on it; `mlp` computes
 the learned initial normals (anchor kNN, features, MLP inference) with the shipped weights;
+`area` the tangent-plane Voronoi area weights (15 neighbours) and the windowed 10-NN radius;
 `copy`
 runs a plain device-to-device copy of a known size, used to calibrate the FETCH_SIZE /
 WRITE_SIZE counters (bytes the counters report per byte actually moved).
@@ -23,7 +25,7 @@ import sys
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["gwn", "copy", "iterate", "tree", "mc", "mlp"])
+    ap.add_argument("what", choices=["gwn", "copy", "iterate", "tree", "mc", "mlp", "area"])
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--lam", type=float, default=10.0)
     ap.add_argument("--reps", type=int, default=2)
@@ -58,6 +60,11 @@ def main(argv=None) -> int:
         mlp = mlp_init.load_params(os.path.join(os.path.dirname(__file__), "weights", "mlp_init.safetensors"), dev)
         for _ in range(args.reps):
             dwg.mlp_normals(P, mlp, ws=ws)
+        torch.cuda.synchronize()
+    elif args.what == "area":
+        for _ in range(args.reps):
+            dwg.voronoi_area(P, 15, ws=ws)
+            dwg.delta_knn_window(P, 10, ws=ws)
         torch.cuda.synchronize()
     elif args.what == "gwn":
         for _ in range(args.reps):
