@@ -280,7 +280,9 @@ dwg_status dwg_delta_knn_mean(const float* P, int64_t n, int k, float scale, flo
  * the threshold of Sec. 5.2, whose absolute distance window assumes the paper's model
  * normalisation: a fixed anchor count fixes the neighbourhood scale relative to the shape,
  * as the paper's octree depth fixes the field's resolution. async. P [3][n]; delta: output
- * [n]; 1 <= k <= 16; n_anchor > k; scale > 0.
+ * [n]; 1 <= k <= 16; n_anchor > k; scale > 0. Workspace: dwg_workspace_bytes(n, n, NULL)
+ * covers n_anchor <= 4096; the anchor grid grows with n_anchor, and a workspace too small
+ * for a larger count gives DWG_E_WORKSPACE with the size needed (dwg_last_error).
  */
 dwg_status dwg_delta_anchor_mean(const float* P, int64_t n, int k, int64_t n_anchor, float scale,
                                  float* delta, void* ws, size_t ws_bytes, void* stream);
@@ -299,7 +301,8 @@ dwg_status dwg_delta_anchor_mean(const float* P, int64_t n, int k, int64_t n_anc
 #define DWG_FEAT_K 16
 int64_t dwg_mlp_param_count(void);
 
-/* Features [n][48] (float32) of every point; n_anchor >= 17. async. */
+/* Features [n][48] (float32) of every point; n_anchor >= 17. async. Workspace as for
+ * dwg_delta_anchor_mean. */
 dwg_status dwg_features(const float* P, int64_t n, int64_t n_anchor, float* feat, void* ws,
                         size_t ws_bytes, void* stream);
 

@@ -626,7 +626,8 @@ dwg_status dwg_delta_anchor_mean(const float* P, int64_t n, int k, int64_t n_anc
   DWG_CHECK(n_anchor > k, "n_anchor must exceed k");
   DWG_CHECK(n > k + 1 && n < (int64_t(1) << 31), "need k + 1 < n < 2^31");
   DWG_CHECK(std::isfinite(scale) && scale > 0.0f, "scale must be finite and > 0");
-  const size_t need = aux_bytes(n);
+  // the anchor grid grows with n_anchor: the requirement is the larger of the two layouts
+  const size_t need = std::max(aux_bytes(n), anchor_ws_bytes(n, feat_chunk(n), n_anchor));
   DWG_CHECK(ws || ws_bytes == 0, "ws is NULL but ws_bytes > 0");
   if (!ws || ws_bytes < need) {
     set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
@@ -652,7 +653,7 @@ dwg_status dwg_features(const float* P, int64_t n, int64_t n_anchor, float* feat
   DWG_CHECK(P && feat, "P and feat must not be NULL");
   DWG_CHECK(n >= DWG_FEAT_K + 2 && n < (int64_t(1) << 31), "n must be in [%d, 2^31)", DWG_FEAT_K + 2);
   DWG_CHECK(n_anchor >= DWG_FEAT_K + 1, "n_anchor must be >= %d", DWG_FEAT_K + 1);
-  const size_t need = aux_bytes(n);
+  const size_t need = std::max(aux_bytes(n), anchor_ws_bytes(n, n, n_anchor));
   DWG_CHECK(ws || ws_bytes == 0, "ws is NULL but ws_bytes > 0");
   if (!ws || ws_bytes < need) {
     set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, need);

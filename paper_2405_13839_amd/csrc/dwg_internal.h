@@ -74,8 +74,10 @@ struct KnnWork {
   int32_t* cursor;   // [max_cells] scatter cursors
   int32_t* sums;     // scan tile totals
   float4* sorted;    // [nr] (x, y, z, index bits) in cell order
+  int32_t* defer;    // [1 + mq] count and list of the queries left to the second search pass
+  int64_t mq;        // most queries of one search call
 };
-size_t carve_knn(Carver& c, int64_t nr, KnnWork* out);
+size_t carve_knn(Carver& c, int64_t nr, int64_t mq, KnnWork* out);
 
 // Anchor features of the learned initial normals: anchors, their grid, chunk buffers.
 constexpr int64_t DWG_FEAT_ANCHORS = 4096;
@@ -88,7 +90,7 @@ struct AnchorCtx {
   KnnWork w;
 };
 size_t carve_anchor(Carver& c, int64_t n, int64_t chunk, int64_t n_anchor, AnchorCtx* out);
-size_t anchor_ws_bytes(int64_t n, int64_t chunk);
+size_t anchor_ws_bytes(int64_t n, int64_t chunk, int64_t n_anchor);
 dwg_status anchor_build(const float* P, int64_t n, const AnchorCtx& x, hipStream_t stream);
 dwg_status anchor_features(const float* P, int64_t n, int64_t q0, int64_t m, const AnchorCtx& x, float* feat,
                            hipStream_t stream);
@@ -191,7 +193,9 @@ dwg_status radix_sort_pairs(uint64_t* const key[2], int32_t* const val[2], int64
 // Bounding box of P and the octree frame (lo xyz, 2^21 / largest extent) in FP64.
 dwg_status morton_frame(const float* P, int64_t n, float* bpart, float* box, double* frame, hipStream_t st);
 // Uniform-grid kNN over reference points: build once, then query [q0, q0 + m) of a planar
-// query array with leading dimension qld (no skipping).
+// query array with leading dimension qld (no skipping; m <= the capacity carved for the grid).
+// One thread searches each query to the end, in the given order: meant for query sets that
+// are already in spatial order.
 dwg_status knn_grid(const float* R, int64_t nr, const KnnWork& w, hipStream_t st);
 dwg_status knn_search(const float* Q, int64_t qld, int64_t q0, int64_t m, const KnnWork& w, int k, int32_t* idx,
                       float* dist, hipStream_t st);

@@ -9,6 +9,7 @@
 // walks Chebyshev rings of cells around its own cell and keeps the k best candidates in
 // registers; it stops once the k-th best distance is below the distance to the next ring.
 #include <cfloat>
+#include <climits>
 #include <cmath>
 
 #include "dwg_internal.h"
@@ -213,20 +214,45 @@ __device__ __forceinline__ bool less_pair(float d2, int i, float e2, int j) {
   return d2 < e2 || (d2 == e2 && i < j);
 }
 
+// Insert (d2, j) into the ascending list bd/bi of K entries, dropping the last (fully
+// unrolled, register resident). The caller has checked that it beats the last entry.
+template <int K>
+__device__ __forceinline__ void insert_sorted(float d2, int j, float* bd, int* bi) {
+#pragma unroll
+  for (int u = K - 1; u >= 1; --u) {
+    const bool up = less_pair(d2, j, bd[u - 1], bi[u - 1]);
+    const bool here = !up && less_pair(d2, j, bd[u], bi[u]);
+    const float nd = up ? bd[u - 1] : (here ? d2 : bd[u]);
+    const int ni = up ? bi[u - 1] : (here ? j : bi[u]);
+    bd[u] = nd;
+    bi[u] = ni;
+  }
+  if (less_pair(d2, j, bd[0], bi[0])) {
+    bd[0] = d2;
+    bi[0] = j;
+  }
+}
+
 // skip_mode: 0 none; 1 reference i == query i; 2 reference i / stride when i % stride == 0.
 // Queries q = 0..m-1 are points q0 + q of the planar array Q with leading dimension qld;
 // results go to idx[q][K], dist[q][K].
-// SELF: the queries are the references themselves (m = their count, skip_mode 1): thread p
+// SELF: the queries are the references themselves (m = their count, skip_mode 1): work item p
 // takes the p-th reference in cell order from `sorted` and writes the row of its original
 // index, so the lanes of a wavefront search neighbouring cells (same results, in another
 // order of work).
+// Two passes, so that a few isolated queries (outliers, whose search spans thousands of
+// cells) do not hold up the wavefronts of everyone else: k_knn (one thread per work item p)
+// searches rings 0..rcap and appends the items it has not finished to defer[1..] (defer[0]
+// counts them); k_knn_wave then searches each deferred item with a whole wavefront. A query's
+// result, the k smallest (distance^2, index) pairs, does not depend on the order in which
+// candidates are met, so it is the same whichever pass finishes it.
 template <int K, bool SELF>
 __global__ __launch_bounds__(256) void k_knn(const float* __restrict__ Q, int64_t qld, int64_t q0,
                                              int64_t m, const GridParams* __restrict__ gp,
                                              const int32_t* __restrict__ start,
                                              const float4* __restrict__ sorted, int skip_mode,
-                                             int64_t stride, int32_t* __restrict__ idx,
-                                             float* __restrict__ dist) {
+                                             int64_t stride, int rcap, int32_t* __restrict__ defer,
+                                             int32_t* __restrict__ idx, float* __restrict__ dist) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= m) return;
   const GridParams g = *gp;
@@ -258,53 +284,190 @@ __global__ __launch_bounds__(256) void k_knn(const float* __restrict__ Q, int64_
   int cx, cy, cz;
   cell_of(g, qx, qy, qz, cx, cy, cz);
   const int rmax = max(g.nx, max(g.ny, g.nz));
-  for (int r = 0; r <= rmax; ++r) {
-    for (int dz = -r; dz <= r; ++dz) {
-      const int z = cz + dz;
-      if (z < 0 || z >= g.nz) continue;
-      for (int dy = -r; dy <= r; ++dy) {
-        const int y = cy + dy;
-        if (y < 0 || y >= g.ny) continue;
-        const bool shell = (dz == -r || dz == r || dy == -r || dy == r);
-        const int xstep = shell ? 1 : max(2 * r, 1);
-        for (int dx = -r; dx <= r; dx += xstep) {
-          const int x = cx + dx;
-          if (x < 0 || x >= g.nx) continue;
-          const int64_t c = ((int64_t)z * g.ny + y) * g.nx + x;
-          const int32_t e = start[c + 1];
-          for (int32_t p = start[c]; p < e; ++p) {
-            const float4 s = sorted[p];
-            const int j = __float_as_int(s.w);
+  // Rings 0..rcap, scanned as rows of consecutive x cells: the cells of one row hold one
+  // contiguous range of `sorted`, so a row costs two loads of `start`. Ring r is the cube of
+  // half-width r minus the cube of half-width r - 1: whole rows where |dz| or |dy| is r, the
+  // two end cells x = cx -+ r elsewhere. Every point outside the cube of half-width r lies
+  // more than r h from the query, which ends the search once the k-th best distance is
+  // within r h; the cube of half-width rmax holds the whole grid.
+  bool done = false;
+  const int rlim = min(rcap, rmax);
+  for (int r = 0; r <= rlim; ++r) {
+    const int zl = max(cz - r, 0), zh = min(cz + r, g.nz - 1);
+    const int yl = max(cy - r, 0), yh = min(cy + r, g.ny - 1);
+    const int xl = max(cx - r, 0), xh = min(cx + r, g.nx - 1);
+    for (int z = zl; z <= zh; ++z) {
+      for (int y = yl; y <= yh; ++y) {
+        const int64_t row = ((int64_t)z * g.ny + y) * g.nx;
+        const bool full = z == cz - r || z == cz + r || y == cy - r || y == cy + r;
+        // segments: the whole row [xl, xh], or its end cells cx - r and cx + r (if inside)
+        int sa0 = xl, sa1 = xh, sb0 = 1, sb1 = 0;
+        if (!full) {
+          sa0 = sa1 = cx - r;
+          sb0 = sb1 = cx + r;
+          if (sa0 < 0) sa1 = sa0 - 1;  // outside the grid: empty segment
+          if (sb0 > g.nx - 1 || r == 0) sb1 = sb0 - 1;
+        }
+        for (int seg = 0; seg < 2; ++seg) {
+          const int x0 = seg == 0 ? sa0 : sb0, x1 = seg == 0 ? sa1 : sb1;
+          if (x0 > x1) continue;
+          const int32_t e = start[row + x1 + 1];
+          for (int32_t pp = start[row + x0]; pp < e; ++pp) {
+            const float4 sp = sorted[pp];
+            const int j = __float_as_int(sp.w);
             if (j == skip) continue;
-            const float ex = s.x - qx, ey = s.y - qy, ez = s.z - qz;
+            const float ex = sp.x - qx, ey = sp.y - qy, ez = sp.z - qz;
             const float d2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
             if (!less_pair(d2, j, bd[K - 1], bi[K - 1])) continue;
-            // insertion into the sorted list (fully unrolled, register resident)
-#pragma unroll
-            for (int t = K - 1; t >= 1; --t) {
-              const bool up = less_pair(d2, j, bd[t - 1], bi[t - 1]);
-              const bool here = !up && less_pair(d2, j, bd[t], bi[t]);
-              const float nd = up ? bd[t - 1] : (here ? d2 : bd[t]);
-              const int ni = up ? bi[t - 1] : (here ? j : bi[t]);
-              bd[t] = nd;
-              bi[t] = ni;
-            }
-            if (less_pair(d2, j, bd[0], bi[0])) {
-              bd[0] = d2;
-              bi[0] = j;
-            }
+            insert_sorted<K>(d2, j, bd, bi);
           }
         }
       }
     }
-    // every cell of ring r + 1 or beyond lies at least r * h away from the query
     const float lb = (float)r * g.h;
-    if (bd[K - 1] < INFINITY && bd[K - 1] <= lb * lb) break;
+    if ((bd[K - 1] < INFINITY && bd[K - 1] <= lb * lb) || r >= rmax) {
+      done = true;
+      break;
+    }
+  }
+  if (!done) {  // left to k_knn_wave
+    defer[1 + atomicAdd(&defer[0], 1)] = (int32_t)p;
+    return;
   }
 #pragma unroll
   for (int s = 0; s < K; ++s) {
     idx[q * K + s] = bi[s];
     if (dist) dist[q * K + s] = sqrtf(bd[s]);
+  }
+}
+
+// Cells of ring r (the cube of half-width r minus the cube of half-width r - 1) and the
+// offset of its l-th cell: first the two faces dz = -r, +r ((2r + 1)^2 cells each, x fastest),
+// then the layers dz = -(r - 1) .. r - 1, each the square ring of side 2r + 1 in (x, y): the
+// rows dy = -r and dy = +r, then the columns dx = -r and dx = +r without their corners.
+__device__ __forceinline__ int ring_cells(int r) { return r == 0 ? 1 : 24 * r * r + 2; }
+__device__ __forceinline__ void ring_cell(int r, int l, int& dx, int& dy, int& dz) {
+  if (r == 0) {
+    dx = dy = dz = 0;
+    return;
+  }
+  const int w = 2 * r + 1, face = w * w;
+  if (l < 2 * face) {
+    dz = l < face ? -r : r;
+    const int rem = l < face ? l : l - face;
+    dy = rem / w - r;
+    dx = rem % w - r;
+    return;
+  }
+  const int lp = l - 2 * face;
+  dz = lp / (8 * r) - (r - 1);
+  const int k = lp % (8 * r);
+  if (k < 2 * w) {
+    dy = k < w ? -r : r;
+    dx = (k < w ? k : k - w) - r;
+  } else {
+    const int kk = k - 2 * w;  // 0 .. 2 (2r - 1) - 1
+    dx = kk < 2 * r - 1 ? -r : r;
+    dy = (kk < 2 * r - 1 ? kk : kk - (2 * r - 1)) - (r - 1);
+  }
+}
+
+// The items k_knn left unfinished, one wavefront per item (a grid-stride loop over the
+// wavefronts of the launch). Ring by ring, the lanes share out the cells of the cube of
+// half-width r (those of the ring itself: max(|dx|, |dy|, |dz|) == r), each walking one cell's
+// points at a time; the list of the k best is the same in every lane, and the candidates
+// that beat its last entry are inserted one by one in lane order (ballot, then a broadcast
+// of each). The ring test is then the exact one of k_knn.
+template <int K, bool SELF>
+__global__ __launch_bounds__(256) void k_knn_wave(const float* __restrict__ Q, int64_t qld, int64_t q0,
+                                                  int64_t m, const GridParams* __restrict__ gp,
+                                                  const int32_t* __restrict__ start,
+                                                  const float4* __restrict__ sorted, int skip_mode,
+                                                  int64_t stride, const int32_t* __restrict__ defer,
+                                                  int32_t* __restrict__ idx, float* __restrict__ dist) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t nd = defer[0];
+  const GridParams g = *gp;
+  const int rmax = max(g.nx, max(g.ny, g.nz));
+  for (int64_t item = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; item < nd; item += nwaves) {
+    const int64_t p = defer[1 + item];
+    int64_t q, gq;
+    float qx, qy, qz;
+    if (SELF) {
+      const float4 sp = sorted[p];
+      q = gq = __float_as_int(sp.w);
+      qx = sp.x;
+      qy = sp.y;
+      qz = sp.z;
+    } else {
+      q = p;
+      gq = q0 + q;
+      qx = Q[gq];
+      qy = Q[qld + gq];
+      qz = Q[2 * qld + gq];
+    }
+    int skip = -1;
+    if (skip_mode == 1) skip = (int)gq;
+    if (skip_mode == 2 && (gq % stride) == 0) skip = (int)(gq / stride);
+    float bd[K];
+    int bi[K];
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+      bd[u] = INFINITY;
+      bi[u] = 0x7fffffff;
+    }
+    int cx, cy, cz;
+    cell_of(g, qx, qy, qz, cx, cy, cz);
+    for (int r = 0; r <= rmax; ++r) {
+      const int cnt = ring_cells(r);
+      for (int l0 = 0; l0 < cnt; l0 += 64) {
+        const int l = l0 + lane;
+        int32_t b = 0, e = 0;
+        if (l < cnt) {
+          int dx, dy, dz;
+          ring_cell(r, l, dx, dy, dz);
+          const int x = cx + dx, y = cy + dy, z = cz + dz;
+          if (x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz) {
+            const int64_t c = ((int64_t)z * g.ny + y) * g.nx + x;
+            b = start[c];
+            e = start[c + 1];
+          }
+        }
+        for (;;) {
+          const bool has = b < e;
+          if (__ballot(has) == 0ull) break;
+          float d2 = INFINITY;
+          int j = 0x7fffffff;
+          bool beat = false;
+          if (has) {
+            const float4 sp = sorted[b];
+            ++b;
+            j = __float_as_int(sp.w);
+            const float ex = sp.x - qx, ey = sp.y - qy, ez = sp.z - qz;
+            d2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+            beat = j != skip && less_pair(d2, j, bd[K - 1], bi[K - 1]);
+          }
+          unsigned long long mask = __ballot(beat);
+          while (mask) {
+            const int src = __ffsll((long long)mask) - 1;
+            mask &= mask - 1ull;
+            const float cd = __shfl(d2, src, 64);
+            const int cj = __shfl(j, src, 64);
+            if (less_pair(cd, cj, bd[K - 1], bi[K - 1])) insert_sorted<K>(cd, cj, bd, bi);
+          }
+        }
+      }
+      const float lb = (float)r * g.h;
+      if (bd[K - 1] < INFINITY && bd[K - 1] <= lb * lb) break;
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int u = 0; u < K; ++u) {
+        idx[q * K + u] = bi[u];
+        if (dist) dist[q * K + u] = sqrtf(bd[u]);
+      }
+    }
   }
 }
 
@@ -587,15 +750,39 @@ unsigned grid_for(int64_t n, int block = 256, int64_t cap = 65535) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, block), cap));
 }
 
+// Rings searched by the thread-per-query pass: with about 8 cells per reference point, a query
+// on a sampled surface meets its neighbours within 2-3 rings (1M torus scene: the self 10-NN
+// finish by ring 2 for 95% of the points, the 16 nearest of 4,096 anchors by ring 3 for 97%);
+// its outliers need 4 to 11.
+constexpr int kFirstPassRings = 3;
+
+// Blocks of the wavefront-per-item pass (4 wavefronts each): 8 wavefronts per SIMD, so that
+// the dependent loads of one item's ring walk overlap with those of others.
+constexpr int kWaveBlocks = 2048;
+
+// two_pass = false: the thread-per-query kernel searches every query to the end (no ring
+// limit, nothing deferred), for query sets whose order already groups the isolated queries
+// together (the level-set faces, emitted cell by cell in Morton order), where a wavefront per
+// deferred query would only spread them out.
+template <int K, bool SELF>
+void launch_knn_t(int64_t m, hipStream_t st, const float* Q, int64_t qld, int64_t q0, const KnnWork& w,
+                  int skip_mode, int64_t stride, bool two_pass, int32_t* idx, float* dist) {
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, w.defer, (int64_t)1);
+  const int rcap = two_pass ? kFirstPassRings : INT_MAX;
+  hipLaunchKernelGGL((k_knn<K, SELF>), dim3((unsigned)cdiv(m, 256)), dim3(256), 0, st, Q, qld, q0, m, w.gp,
+                     w.start, w.sorted, skip_mode, stride, rcap, w.defer, idx, dist);
+  if (two_pass)
+    hipLaunchKernelGGL((k_knn_wave<K, SELF>), dim3(kWaveBlocks), dim3(256), 0, st, Q, qld, q0, m, w.gp, w.start,
+                       w.sorted, skip_mode, stride, w.defer, idx, dist);
+}
+
 template <int K>
 void launch_knn_k(int64_t m, hipStream_t st, const float* Q, int64_t qld, int64_t q0, const KnnWork& w,
-                  int skip_mode, int64_t stride, bool self, int32_t* idx, float* dist) {
+                  int skip_mode, int64_t stride, bool self, bool two_pass, int32_t* idx, float* dist) {
   if (self)
-    hipLaunchKernelGGL((k_knn<K, true>), dim3((unsigned)cdiv(m, 256)), dim3(256), 0, st, Q, qld, q0, m, w.gp,
-                       w.start, w.sorted, skip_mode, stride, idx, dist);
+    launch_knn_t<K, true>(m, st, Q, qld, q0, w, skip_mode, stride, two_pass, idx, dist);
   else
-    hipLaunchKernelGGL((k_knn<K, false>), dim3((unsigned)cdiv(m, 256)), dim3(256), 0, st, Q, qld, q0, m, w.gp,
-                       w.start, w.sorted, skip_mode, stride, idx, dist);
+    launch_knn_t<K, false>(m, st, Q, qld, q0, w, skip_mode, stride, two_pass, idx, dist);
 }
 
 dwg_status build_grid(const float* R, int64_t nr, const KnnWork& w, hipStream_t st) {
@@ -625,10 +812,16 @@ dwg_status build_grid(const float* R, int64_t nr, const KnnWork& w, hipStream_t 
 
 // self: the queries are exactly the m references of the grid, q0 = 0, skip_mode 1.
 dwg_status knn_query(const float* Q, int64_t qld, int64_t q0, int64_t m, const KnnWork& w, int skip_mode,
-                     int64_t stride, int k, int32_t* idx, float* dist, hipStream_t st, bool self = false) {
+                     int64_t stride, int k, int32_t* idx, float* dist, hipStream_t st, bool self = false,
+                     bool two_pass = true) {
+  if (m > w.mq) {  // the deferred list holds at most w.mq items
+    set_error("internal: %lld kNN queries exceed the carved capacity %lld", (long long)m, (long long)w.mq);
+    return DWG_E_INVALID;
+  }
+  if (m <= 0) return DWG_OK;
   switch (k) {
 #define DWG_K(KK) \
-  case KK: launch_knn_k<KK>(m, st, Q, qld, q0, w, skip_mode, stride, self, idx, dist); break;
+  case KK: launch_knn_k<KK>(m, st, Q, qld, q0, w, skip_mode, stride, self, two_pass, idx, dist); break;
     DWG_K(1) DWG_K(2) DWG_K(3) DWG_K(4) DWG_K(5) DWG_K(6) DWG_K(7) DWG_K(8)
     DWG_K(9) DWG_K(10) DWG_K(11) DWG_K(12) DWG_K(13) DWG_K(14) DWG_K(15) DWG_K(16)
 #undef DWG_K
@@ -644,13 +837,15 @@ dwg_status knn_grid(const float* R, int64_t nr, const KnnWork& w, hipStream_t st
 
 dwg_status knn_search(const float* Q, int64_t qld, int64_t q0, int64_t m, const KnnWork& w, int k, int32_t* idx,
                       float* dist, hipStream_t st) {
-  return knn_query(Q, qld, q0, m, w, 0, 1, k, idx, dist, st);
+  return knn_query(Q, qld, q0, m, w, 0, 1, k, idx, dist, st, false, false);
 }
 
-size_t carve_knn(Carver& c, int64_t nr, KnnWork* out) {
+size_t carve_knn(Carver& c, int64_t nr, int64_t mq, KnnWork* out) {
   const int64_t mc = max_cells_for(nr);
   const size_t s0 = c.used;
   KnnWork w;
+  w.mq = mq;
+  w.defer = c.take<int32_t>((size_t)mq + 1);
   w.bbox_part = c.take<float>(kBboxBlocks * 6);
   w.gp = c.take<GridParams>(1);
   w.key = c.take<int32_t>((size_t)nr);
@@ -686,7 +881,7 @@ dwg_status exclusive_scan(int32_t* a, int64_t n, int32_t* sums, hipStream_t st) 
 size_t knn_ws_bytes(int64_t n_ref, int64_t n_qry) {
   (void)n_qry;
   Carver c(nullptr);
-  carve_knn(c, n_ref, nullptr);
+  carve_knn(c, n_ref, n_qry, nullptr);
   return c.used;
 }
 
@@ -697,7 +892,7 @@ dwg_status knn_run(const float* R, int64_t nr, const float* Q, int64_t m, int se
   (void)skip_stride;
   Carver c(ws);
   KnnWork w;
-  carve_knn(c, nr, &w);
+  carve_knn(c, nr, m, &w);
   dwg_status s = build_grid(R, nr, w, stream);
   if (s != DWG_OK) return s;
   // queries that are the references themselves (same array, same count) run in cell order
@@ -712,10 +907,10 @@ dwg_status delta_from_knn(const float* dist, int64_t n, int k, float scale, floa
   return DWG_OK;
 }
 
-size_t anchor_ws_bytes(int64_t n, int64_t chunk) {
+size_t anchor_ws_bytes(int64_t n, int64_t chunk, int64_t n_anchor) {
   Carver c(nullptr);
   AnchorCtx x;
-  carve_anchor(c, n, chunk, DWG_FEAT_ANCHORS, &x);
+  carve_anchor(c, n, chunk, n_anchor, &x);
   return c.used;
 }
 
@@ -729,7 +924,7 @@ size_t carve_anchor(Carver& c, int64_t n, int64_t chunk, int64_t n_anchor, Ancho
   x.idx = c.take<int32_t>((size_t)chunk * DWG_FEAT_K);
   x.dist = c.take<float>((size_t)chunk * DWG_FEAT_K);
   x.feat = c.take<float>((size_t)chunk * DWG_MLP_IN);
-  carve_knn(c, x.na, &x.w);
+  carve_knn(c, x.na, chunk, &x.w);
   if (out) *out = x;
   return c.used - s0;
 }

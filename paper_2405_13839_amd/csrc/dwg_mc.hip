@@ -429,7 +429,7 @@ size_t carve_mc_faces(Carver& c, int64_t n, int64_t C, int k, McWork* w) {
   o->idx = c.take<int32_t>((size_t)(o->chunk * k));
   o->dist = c.take<float>((size_t)(o->chunk * k));
   o->acc = c.take<unsigned long long>((size_t)(3 * n));
-  carve_knn(c, n, &o->knn);
+  carve_knn(c, n, o->chunk, &o->knn);
   return c.used - s0;
 }
 
