@@ -474,8 +474,12 @@ __device__ __forceinline__ void fold(float* sum, float* cmp, const float* acc) {
 
 // Traversal: one thread per sorted query, one node index per wavefront (see the file head).
 // Contributions are summed in FP32 into `acc` and folded into the (Kahan-compensated when
-// KAHAN) running sums after every leaf visit and at the end. The next node is usually i + 1
-// (a node opened, or a leaf, whose skip is i + 1), so its data is loaded one step ahead.
+// KAHAN) running sums after every kFoldLeaves leaf visits of the wavefront and at the end
+// (a fold is 4 VALU per accumulator; folding after every visit was ~2% slower at 1M). The
+// next node is usually i + 1 (a node opened, or a leaf, whose skip is i + 1), so its data is
+// loaded one step ahead.
+constexpr int kFoldLeaves = 4;
+
 template <bool GRAD, bool SCREENED, bool KAHAN>
 __global__ __launch_bounds__(256) void k_tree_eval(const float* __restrict__ Q, int64_t m,
                                                    const int32_t* __restrict__ qperm, const int4* __restrict__ node,
@@ -497,6 +501,7 @@ __global__ __launch_bounds__(256) void k_tree_eval(const float* __restrict__ Q, 
   if (nn > cap) nn = (int)cap;
   int skip_to = 0;
   int i = 0;
+  int visits = 0;  // leaf visits of the wavefront since the last fold
   int4 nd = node[0];
   double4 g = geo[0];
   float4 mm = mom[0];
@@ -541,9 +546,12 @@ __global__ __launch_bounds__(256) void k_tree_eval(const float* __restrict__ Q, 
               pair_plain<GRAD, false>(a, b, qx, qy, qz, acc);
           }
         }
-        fold<NA, KAHAN>(sum, cmp, acc);
+        if (++visits == kFoldLeaves) {
+          visits = 0;
+          fold<NA, KAHAN>(sum, cmp, acc);
 #pragma unroll
-        for (int a = 0; a < NA; ++a) acc[a] = 0.0f;
+          for (int a = 0; a < NA; ++a) acc[a] = 0.0f;
+        }
       }
       next = nskip > i ? nskip : i + 1;  // pre-order: skip > i always; guards the loop regardless
     }
