@@ -133,6 +133,42 @@ def test_knn_and_delta_match_oracle(n, k):
     np.testing.assert_allclose(delta[sel], rdist.mean(axis=1), rtol=3e-6)
 
 
+@pytest.mark.parametrize("k", [1, 10, 16])
+def test_knn_queries_far_from_the_references(k):
+    """Queries that are not the references: points near the surfaces, points uniform in a box
+    three times the references' (many outside the grid) and a cluster far away, so that both
+    search passes run (a thread per query up to ring 3, a wavefront per unfinished one)."""
+    dwg = _dwg()
+    R = synth.torus_ellipsoids(20_000, seed=33).P
+    rng = np.random.default_rng(7)
+    near = R[:, rng.choice(R.shape[1], 2000, replace=False)] + rng.normal(0, 0.01, (3, 2000))
+    box = rng.uniform(-6, 6, (3, 2000))
+    far = np.array([[20.0], [20.0], [20.0]]) + rng.normal(0, 0.5, (3, 100))
+    Q = np.concatenate([near, box, far], axis=1).astype(np.float32)
+    idx, dist = dwg.knn(cuda(R), cuda(Q), k)
+    idx, dist = host(idx), host(dist).astype(np.float64)
+    _, rdist = oracle.knn(R, Q, k)
+    np.testing.assert_allclose(dist, rdist, rtol=2e-6, atol=1e-7)
+    true_d = np.linalg.norm(R[:, idx].astype(np.float64) - Q[:, :, None].astype(np.float64), axis=0)
+    np.testing.assert_allclose(true_d, rdist, rtol=2e-6, atol=1e-7)
+    for row in idx:
+        assert len(set(row.tolist())) == k
+
+
+def test_knn_self_full_size_sampled():
+    """Self 15-NN at 1M points (the Voronoi-area configuration of the benchmark cloud, 5%
+    outliers); 2000 sampled queries recomputed by the oracle."""
+    dwg = _dwg()
+    c = synth.torus_ellipsoids(1_000_000, seed=102)
+    Pc = cuda(c.P)
+    idx, dist = dwg.knn(Pc, Pc, 15, self_skip=True)
+    sel = np.random.default_rng(4).choice(c.n, 2000, replace=False)
+    idx, dist = host(idx)[sel], host(dist)[sel].astype(np.float64)
+    _, rdist = oracle.knn(c.P, c.P[:, sel], 15, skip=sel)
+    np.testing.assert_allclose(dist, rdist, rtol=2e-6, atol=1e-7)
+    assert np.all(idx != sel[:, None])
+
+
 def test_one_iteration_sampled_at_100k():
     """One screened iteration on 100K points (torus + ellipsoids): the GPU's new normals at 500
     sampled points equal -grad w / |grad w| of the oracle's field of the initial normals."""
