@@ -341,43 +341,13 @@ __global__ __launch_bounds__(256) void k_knn(const float* __restrict__ Q, int64_
   }
 }
 
-// Cells of ring r (the cube of half-width r minus the cube of half-width r - 1) and the
-// offset of its l-th cell: first the two faces dz = -r, +r ((2r + 1)^2 cells each, x fastest),
-// then the layers dz = -(r - 1) .. r - 1, each the square ring of side 2r + 1 in (x, y): the
-// rows dy = -r and dy = +r, then the columns dx = -r and dx = +r without their corners.
-__device__ __forceinline__ int ring_cells(int r) { return r == 0 ? 1 : 24 * r * r + 2; }
-__device__ __forceinline__ void ring_cell(int r, int l, int& dx, int& dy, int& dz) {
-  if (r == 0) {
-    dx = dy = dz = 0;
-    return;
-  }
-  const int w = 2 * r + 1, face = w * w;
-  if (l < 2 * face) {
-    dz = l < face ? -r : r;
-    const int rem = l < face ? l : l - face;
-    dy = rem / w - r;
-    dx = rem % w - r;
-    return;
-  }
-  const int lp = l - 2 * face;
-  dz = lp / (8 * r) - (r - 1);
-  const int k = lp % (8 * r);
-  if (k < 2 * w) {
-    dy = k < w ? -r : r;
-    dx = (k < w ? k : k - w) - r;
-  } else {
-    const int kk = k - 2 * w;  // 0 .. 2 (2r - 1) - 1
-    dx = kk < 2 * r - 1 ? -r : r;
-    dy = (kk < 2 * r - 1 ? kk : kk - (2 * r - 1)) - (r - 1);
-  }
-}
-
 // The items k_knn left unfinished, one wavefront per item (a grid-stride loop over the
-// wavefronts of the launch). Ring by ring, the lanes share out the cells of the cube of
-// half-width r (those of the ring itself: max(|dx|, |dy|, |dz|) == r), each walking one cell's
-// points at a time; the list of the k best is the same in every lane, and the candidates
-// that beat its last entry are inserted one by one in lane order (ballot, then a broadcast
-// of each). The ring test is then the exact one of k_knn.
+// wavefronts of the launch). Ring by ring, the lanes share out the ring's rows of cells
+// inside the grid (the rows of k_knn: whole rows where |dz| or |dy| is r, the two end cells
+// elsewhere), each walking its row's one or two ranges of `sorted` a point at a time; the
+// list of the k best is the same in every lane, and the candidates that beat its last entry
+// are inserted one by one in lane order (ballot, then a broadcast of each). The ring test is
+// then the exact one of k_knn. The work per ring is bounded by the grid's rows.
 template <int K, bool SELF>
 __global__ __launch_bounds__(256) void k_knn_wave(const float* __restrict__ Q, int64_t qld, int64_t q0,
                                                   int64_t m, const GridParams* __restrict__ gp,
@@ -420,29 +390,40 @@ __global__ __launch_bounds__(256) void k_knn_wave(const float* __restrict__ Q, i
     int cx, cy, cz;
     cell_of(g, qx, qy, qz, cx, cy, cz);
     for (int r = 0; r <= rmax; ++r) {
-      const int cnt = ring_cells(r);
-      for (int l0 = 0; l0 < cnt; l0 += 64) {
-        const int l = l0 + lane;
-        int32_t b = 0, e = 0;
-        if (l < cnt) {
-          int dx, dy, dz;
-          ring_cell(r, l, dx, dy, dz);
-          const int x = cx + dx, y = cy + dy, z = cz + dz;
-          if (x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz) {
-            const int64_t c = ((int64_t)z * g.ny + y) * g.nx + x;
-            b = start[c];
-            e = start[c + 1];
+      const int zl = max(cz - r, 0), zh = min(cz + r, g.nz - 1);
+      const int yl = max(cy - r, 0), yh = min(cy + r, g.ny - 1);
+      const int xl = max(cx - r, 0), xh = min(cx + r, g.nx - 1);
+      const int nyr = yh - yl + 1;
+      const int64_t rows = (int64_t)(zh - zl + 1) * nyr;
+      for (int64_t l0 = 0; l0 < rows; l0 += 64) {
+        const int64_t l = l0 + lane;
+        int32_t b0 = 0, e0 = 0, b1 = 0, e1 = 0;  // this lane's row: up to two ranges of sorted
+        if (l < rows) {
+          const int z = zl + (int)(l / nyr), y = yl + (int)(l % nyr);
+          const int64_t row = ((int64_t)z * g.ny + y) * g.nx;
+          if (z == cz - r || z == cz + r || y == cy - r || y == cy + r) {
+            b0 = start[row + xl];
+            e0 = start[row + xh + 1];
+          } else {
+            if (cx - r >= 0) {
+              b0 = start[row + cx - r];
+              e0 = start[row + cx - r + 1];
+            }
+            if (r > 0 && cx + r <= g.nx - 1) {
+              b1 = start[row + cx + r];
+              e1 = start[row + cx + r + 1];
+            }
           }
         }
         for (;;) {
-          const bool has = b < e;
+          const bool has = b0 < e0 || b1 < e1;
           if (__ballot(has) == 0ull) break;
           float d2 = INFINITY;
           int j = 0x7fffffff;
           bool beat = false;
           if (has) {
-            const float4 sp = sorted[b];
-            ++b;
+            const int32_t pp = b0 < e0 ? b0++ : b1++;
+            const float4 sp = sorted[pp];
             j = __float_as_int(sp.w);
             const float ex = sp.x - qx, ey = sp.y - qy, ez = sp.z - qz;
             d2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));

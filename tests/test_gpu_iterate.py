@@ -155,6 +155,29 @@ def test_knn_queries_far_from_the_references(k):
         assert len(set(row.tolist())) == k
 
 
+@pytest.mark.parametrize("shape", ["line", "plane"])
+def test_knn_degenerate_reference_sets(shape):
+    """References on a segment or exactly in a plane (a grid one cell thick in two or one
+    dimensions) and queries up to a unit away from them, so that the searches run to
+    thousands of rings along the thin grid."""
+    dwg = _dwg()
+    rng = np.random.default_rng(11)
+    n = 20_000
+    R = np.zeros((3, n))
+    R[0] = rng.uniform(0, 1, n)
+    if shape == "plane":
+        R[1] = rng.uniform(0, 1, n)
+    R = R.astype(np.float32)
+    Q = np.concatenate([R[:, :500] + rng.normal(0, 1e-3, (3, 500)), rng.uniform(-1, 2, (3, 1500))],
+                       axis=1).astype(np.float32)
+    idx, dist = dwg.knn(cuda(R), cuda(Q), 10)
+    _, rdist = oracle.knn(R, Q, 10)
+    np.testing.assert_allclose(host(dist).astype(np.float64), rdist, rtol=2e-6, atol=1e-7)
+    idx = host(idx)
+    true_d = np.linalg.norm(R[:, idx].astype(np.float64) - Q[:, :, None].astype(np.float64), axis=0)
+    np.testing.assert_allclose(true_d, rdist, rtol=2e-6, atol=1e-7)
+
+
 def test_knn_self_full_size_sampled():
     """Self 15-NN at 1M points (the Voronoi-area configuration of the benchmark cloud, 5%
     outliers); 2000 sampled queries recomputed by the oracle."""
