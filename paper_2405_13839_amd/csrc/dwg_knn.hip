@@ -233,6 +233,63 @@ __device__ __forceinline__ void insert_sorted(float d2, int j, float* bd, int* b
   }
 }
 
+// A query of the search: output row q, position, and the reference index it skips (-1: none).
+struct KnnQuery {
+  int64_t q;
+  float x, y, z;
+  int skip;
+};
+
+// Work item p (see k_knn): the p-th reference in cell order (SELF) or query q0 + p of Q.
+template <bool SELF>
+__device__ __forceinline__ KnnQuery knn_query_of(int64_t p, const float* __restrict__ Q, int64_t qld, int64_t q0,
+                                                 const float4* __restrict__ sorted, int skip_mode, int64_t stride) {
+  KnnQuery k;
+  int64_t gq;
+  if (SELF) {
+    const float4 sp = sorted[p];
+    k.q = gq = __float_as_int(sp.w);
+    k.x = sp.x;
+    k.y = sp.y;
+    k.z = sp.z;
+  } else {
+    k.q = p;
+    gq = q0 + p;
+    k.x = Q[gq];
+    k.y = Q[qld + gq];
+    k.z = Q[2 * qld + gq];
+  }
+  k.skip = -1;
+  if (skip_mode == 1) k.skip = (int)gq;
+  if (skip_mode == 2 && (gq % stride) == 0) k.skip = (int)(gq / stride);
+  return k;
+}
+
+// The cells of ring r (the cube of half-width r around cell (cx, cy, cz) minus the cube of
+// half-width r - 1) in the grid row (z, y), as at most two ranges [b0, e0), [b1, e1) of
+// `sorted`: the whole row [xl, xh] (clipped to the grid) when |z - cz| or |y - cy| is r, else
+// its end cells cx - r and cx + r where they are inside the grid. The cells of a row are
+// consecutive, so a range costs two loads of `start` however many cells it spans.
+__device__ __forceinline__ void ring_row(const GridParams& g, const int32_t* __restrict__ start, int cx, int cy,
+                                         int cz, int r, int z, int y, int xl, int xh, int32_t& b0, int32_t& e0,
+                                         int32_t& b1, int32_t& e1) {
+  const int64_t row = ((int64_t)z * g.ny + y) * g.nx;
+  b0 = e0 = b1 = e1 = 0;
+  if (z == cz - r || z == cz + r || y == cy - r || y == cy + r) {
+    b0 = start[row + xl];
+    e0 = start[row + xh + 1];
+    return;
+  }
+  if (cx - r >= 0) {
+    b0 = start[row + cx - r];
+    e0 = start[row + cx - r + 1];
+  }
+  if (r > 0 && cx + r <= g.nx - 1) {
+    b1 = start[row + cx + r];
+    e1 = start[row + cx + r + 1];
+  }
+}
+
 // skip_mode: 0 none; 1 reference i == query i; 2 reference i / stride when i % stride == 0.
 // Queries q = 0..m-1 are points q0 + q of the planar array Q with leading dimension qld;
 // results go to idx[q][K], dist[q][K].
@@ -256,24 +313,10 @@ __global__ __launch_bounds__(256) void k_knn(const float* __restrict__ Q, int64_
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= m) return;
   const GridParams g = *gp;
-  int64_t q, gq;
-  float qx, qy, qz;
-  if (SELF) {
-    const float4 sp = sorted[p];
-    q = gq = __float_as_int(sp.w);
-    qx = sp.x;
-    qy = sp.y;
-    qz = sp.z;
-  } else {
-    q = p;
-    gq = q0 + q;
-    qx = Q[gq];
-    qy = Q[qld + gq];
-    qz = Q[2 * qld + gq];
-  }
-  int skip = -1;
-  if (skip_mode == 1) skip = (int)gq;
-  if (skip_mode == 2 && (gq % stride) == 0) skip = (int)(gq / stride);
+  const KnnQuery kq = knn_query_of<SELF>(p, Q, qld, q0, sorted, skip_mode, stride);
+  const int64_t q = kq.q;
+  const float qx = kq.x, qy = kq.y, qz = kq.z;
+  const int skip = kq.skip;
   float bd[K];
   int bi[K];
 #pragma unroll
@@ -284,12 +327,9 @@ __global__ __launch_bounds__(256) void k_knn(const float* __restrict__ Q, int64_
   int cx, cy, cz;
   cell_of(g, qx, qy, qz, cx, cy, cz);
   const int rmax = max(g.nx, max(g.ny, g.nz));
-  // Rings 0..rcap, scanned as rows of consecutive x cells: the cells of one row hold one
-  // contiguous range of `sorted`, so a row costs two loads of `start`. Ring r is the cube of
-  // half-width r minus the cube of half-width r - 1: whole rows where |dz| or |dy| is r, the
-  // two end cells x = cx -+ r elsewhere. Every point outside the cube of half-width r lies
-  // more than r h from the query, which ends the search once the k-th best distance is
-  // within r h; the cube of half-width rmax holds the whole grid.
+  // Rings 0..rcap, a row of cells at a time (ring_row). Every point outside the cube of
+  // half-width r lies more than r h from the query, which ends the search once the k-th best
+  // distance is within r h; the cube of half-width rmax holds the whole grid.
   bool done = false;
   const int rlim = min(rcap, rmax);
   for (int r = 0; r <= rlim; ++r) {
@@ -298,21 +338,11 @@ __global__ __launch_bounds__(256) void k_knn(const float* __restrict__ Q, int64_
     const int xl = max(cx - r, 0), xh = min(cx + r, g.nx - 1);
     for (int z = zl; z <= zh; ++z) {
       for (int y = yl; y <= yh; ++y) {
-        const int64_t row = ((int64_t)z * g.ny + y) * g.nx;
-        const bool full = z == cz - r || z == cz + r || y == cy - r || y == cy + r;
-        // segments: the whole row [xl, xh], or its end cells cx - r and cx + r (if inside)
-        int sa0 = xl, sa1 = xh, sb0 = 1, sb1 = 0;
-        if (!full) {
-          sa0 = sa1 = cx - r;
-          sb0 = sb1 = cx + r;
-          if (sa0 < 0) sa1 = sa0 - 1;  // outside the grid: empty segment
-          if (sb0 > g.nx - 1 || r == 0) sb1 = sb0 - 1;
-        }
+        int32_t b0, e0, b1, e1;
+        ring_row(g, start, cx, cy, cz, r, z, y, xl, xh, b0, e0, b1, e1);
         for (int seg = 0; seg < 2; ++seg) {
-          const int x0 = seg == 0 ? sa0 : sb0, x1 = seg == 0 ? sa1 : sb1;
-          if (x0 > x1) continue;
-          const int32_t e = start[row + x1 + 1];
-          for (int32_t pp = start[row + x0]; pp < e; ++pp) {
+          const int32_t e = seg == 0 ? e0 : e1;
+          for (int32_t pp = seg == 0 ? b0 : b1; pp < e; ++pp) {
             const float4 sp = sorted[pp];
             const int j = __float_as_int(sp.w);
             if (j == skip) continue;
@@ -361,25 +391,10 @@ __global__ __launch_bounds__(256) void k_knn_wave(const float* __restrict__ Q, i
   const GridParams g = *gp;
   const int rmax = max(g.nx, max(g.ny, g.nz));
   for (int64_t item = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; item < nd; item += nwaves) {
-    const int64_t p = defer[1 + item];
-    int64_t q, gq;
-    float qx, qy, qz;
-    if (SELF) {
-      const float4 sp = sorted[p];
-      q = gq = __float_as_int(sp.w);
-      qx = sp.x;
-      qy = sp.y;
-      qz = sp.z;
-    } else {
-      q = p;
-      gq = q0 + q;
-      qx = Q[gq];
-      qy = Q[qld + gq];
-      qz = Q[2 * qld + gq];
-    }
-    int skip = -1;
-    if (skip_mode == 1) skip = (int)gq;
-    if (skip_mode == 2 && (gq % stride) == 0) skip = (int)(gq / stride);
+    const KnnQuery kq = knn_query_of<SELF>(defer[1 + item], Q, qld, q0, sorted, skip_mode, stride);
+    const int64_t q = kq.q;
+    const float qx = kq.x, qy = kq.y, qz = kq.z;
+    const int skip = kq.skip;
     float bd[K];
     int bi[K];
 #pragma unroll
@@ -398,23 +413,8 @@ __global__ __launch_bounds__(256) void k_knn_wave(const float* __restrict__ Q, i
       for (int64_t l0 = 0; l0 < rows; l0 += 64) {
         const int64_t l = l0 + lane;
         int32_t b0 = 0, e0 = 0, b1 = 0, e1 = 0;  // this lane's row: up to two ranges of sorted
-        if (l < rows) {
-          const int z = zl + (int)(l / nyr), y = yl + (int)(l % nyr);
-          const int64_t row = ((int64_t)z * g.ny + y) * g.nx;
-          if (z == cz - r || z == cz + r || y == cy - r || y == cy + r) {
-            b0 = start[row + xl];
-            e0 = start[row + xh + 1];
-          } else {
-            if (cx - r >= 0) {
-              b0 = start[row + cx - r];
-              e0 = start[row + cx - r + 1];
-            }
-            if (r > 0 && cx + r <= g.nx - 1) {
-              b1 = start[row + cx + r];
-              e1 = start[row + cx + r + 1];
-            }
-          }
-        }
+        if (l < rows)
+          ring_row(g, start, cx, cy, cz, r, zl + (int)(l / nyr), yl + (int)(l % nyr), xl, xh, b0, e0, b1, e1);
         for (;;) {
           const bool has = b0 < e0 || b1 < e1;
           if (__ballot(has) == 0ull) break;
