@@ -31,15 +31,19 @@ FLOP_PER_PAIR = {False: 32, True: 44}  # algorithmic FLOP per (query, source) pa
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (256 CU x 2.4 GHz x 256 FLOP/clk)
 WEIGHTS = os.path.join(ROOT, "paper_2405_13839_amd", "weights", "mlp_init.safetensors")
 TRAFFIC = os.path.join(ROOT, "profiles", "gwn_traffic.json")
-GWN_SRC = [os.path.join(ROOT, "paper_2405_13839_amd", "csrc", f) for f in ("dwg_gwn.hip", "dwg_pair.h", "dwg_internal.h")]
+GWN_SRC = [os.path.join(ROOT, "paper_2405_13839_amd", "csrc", f) for f in ("dwg_gwn.hip", "dwg_pair.h")]
+GWN_CONSTANTS = os.path.join(ROOT, "paper_2405_13839_amd", "csrc", "dwg_internal.h")
 
 
 def kernel_sha() -> str:
-    """Hash of the all-pairs kernel's sources (its file, the shared pair arithmetic and the
-    tile / split constants)."""
+    """Hash of the all-pairs kernel's sources: its file, the shared pair arithmetic and the
+    `constexpr` lines of the internal header (tile, block and split constants)."""
     h = hashlib.sha256()
     for f in GWN_SRC:
         h.update(open(f, "rb").read())
+    for line in open(GWN_CONSTANTS, "rb"):
+        if line.lstrip().startswith(b"constexpr"):
+            h.update(line)
     return h.hexdigest()[:16]
 
 
