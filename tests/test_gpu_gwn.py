@@ -82,6 +82,25 @@ def test_eps_floor_and_zero_delta_are_the_same_kernel():
     assert torch.equal(w3, w4) and torch.equal(g3, g4)
 
 
+@pytest.mark.parametrize("lam", [0.0, 10.0])
+def test_duplicate_sources(lam):
+    """Exact duplicates among the sources (a point repeated three times, with different normals
+    and areas): every copy at distance 0 from a query contributes nothing, the others count in
+    full; the queries are the sources themselves, so each duplicate group meets both cases."""
+    dwg = _dwg()
+    P, N, a, d = _cloud(1500, 21)
+    rng = np.random.default_rng(22)
+    dup = rng.choice(1500, 60, replace=False)
+    P = np.concatenate([P, P[:, dup], P[:, dup]], axis=1)
+    N = np.concatenate([N, unit_rows(rng, 120)], axis=1)
+    a = np.concatenate([a, a[dup], 2 * a[dup]]).astype(np.float32)
+    d = np.concatenate([d, d[dup], d[dup]]).astype(np.float32)
+    w, g = dwg.gwn(cuda(P), cuda(N), cuda(a), cuda(d), cuda(P), dwg.Params(lam=lam))
+    w_ref, g_ref, flag = oracle.gwn(P, N, a, d, P, lam=lam)
+    assert e_w(host(w), w_ref) <= TOL_W
+    assert e_g(host(g), g_ref, skip=flag) <= TOL_G
+
+
 def test_sphere_closed_form_on_gpu():
     """Screened GWN of a sphere with exact normals (closed form) evaluated by the kernel."""
     dwg = _dwg()
