@@ -589,13 +589,14 @@ __global__ void k_pca_normals(const float* __restrict__ P, int64_t n, const int3
 // Area weight of p_i (Sec. 5.1 "Computing Area Weights"): the plane through p_i normal to the
 // smallest-eigenvalue eigenvector of the covariance of p_i and its m nearest other points
 // (FP64), those points projected onto it, and the area of p_i's cell in the 2D Voronoi
-// diagram of the projections: the half-planes x . q_j <= |q_j|^2 / 2 clipped (Sutherland-
-// Hodgman) starting from the square [-R, R]^2, R = the largest projected distance, which
-// bounds the cell of a point whose neighbours lie on one side; the square's axes are
-// u = n x e_k / |n x e_k| (e_k the axis with the smallest |n_k|, the first on ties) and n x u. Coincident neighbours
-// (q_j = 0) bound nothing and are skipped; all-coincident neighbourhoods give 0.
-__global__ void k_voronoi_area(const float* __restrict__ P, int64_t n, const int32_t* __restrict__ idx, int m,
-                               float* __restrict__ area) {
+// diagram of the projections: the square [-R, R]^2 (R = the largest projected distance, which
+// bounds the cell of a point whose neighbours lie on one side) cut by the half-planes
+// x . q_j <= |q_j|^2 / 2; the square's axes are u = n x e_k / |n x e_k| (e_k the axis with the
+// smallest |n_k|, the first on ties) and n x u. Coincident neighbours (q_j = 0) bound nothing
+// and are skipped; all-coincident neighbourhoods give 0.
+__global__ __launch_bounds__(128) void k_voronoi_area(const float* __restrict__ P, int64_t n,
+                                                     const int32_t* __restrict__ idx, int m,
+                                                     float* __restrict__ area) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double px = P[i], py = P[n + i], pz = P[2 * n + i];
@@ -634,58 +635,80 @@ __global__ void k_voronoi_area(const float* __restrict__ P, int64_t n, const int
   u1 /= ul;
   u2 /= ul;
   const double w0 = nv[1] * u2 - nv[2] * u1, w1 = nv[2] * u0 - nv[0] * u2, w2 = nv[0] * u1 - nv[1] * u0;
-  double qx[kMaxK], qy[kMaxK];
+  double qx[kMaxK], qy[kMaxK];  // unrolled to the compile-time maximum: register resident
   double R = 0.0;
-  for (int t = 0; t < m; ++t) {
-    const int64_t j = idx[i * m + t];
-    const double dx = P[j] - px, dy = P[n + j] - py, dz = P[2 * n + j] - pz;
-    qx[t] = dx * u0 + dy * u1 + dz * u2;
-    qy[t] = dx * w0 + dy * w1 + dz * w2;
-    const double r = sqrt(qx[t] * qx[t] + qy[t] * qy[t]);
-    R = r > R ? r : R;
+#pragma unroll
+  for (int t = 0; t < kMaxK; ++t) {
+    qx[t] = qy[t] = 0.0;
+    if (t < m) {
+      const int64_t j = idx[i * m + t];
+      const double dx = P[j] - px, dy = P[n + j] - py, dz = P[2 * n + j] - pz;
+      qx[t] = dx * u0 + dy * u1 + dz * u2;
+      qy[t] = dx * w0 + dy * w1 + dz * w2;
+      const double r = sqrt(qx[t] * qx[t] + qy[t] * qy[t]);
+      R = r > R ? r : R;
+    }
   }
   if (!(R > 0.0)) {
     area[i] = 0.0f;
     return;
   }
-  constexpr int kMaxV = kMaxK + 6;
-  double vx[2][kMaxV], vy[2][kMaxV];
-  int nvtx = 4, cur = 0;
-  vx[0][0] = -R, vy[0][0] = -R;
-  vx[0][1] = R, vy[0][1] = -R;
-  vx[0][2] = R, vy[0][2] = R;
-  vx[0][3] = -R, vy[0][3] = R;
-  for (int t = 0; t < m && nvtx > 0; ++t) {
-    const double qa = qx[t], qb = qy[t];
-    const double qc = 0.5 * (qa * qa + qb * qb);
-    if (qc == 0.0) continue;
-    const int nxt = cur ^ 1;
-    int out = 0;
-    for (int v = 0; v < nvtx; ++v) {
-      const int v2 = v + 1 == nvtx ? 0 : v + 1;
-      const double s1 = qa * vx[cur][v] + qb * vy[cur][v] - qc;
-      const double s2 = qa * vx[cur][v2] + qb * vy[cur][v2] - qc;
-      if (s1 <= 0.0 && out < kMaxV) {
-        vx[nxt][out] = vx[cur][v];
-        vy[nxt][out] = vy[cur][v];
-        ++out;
+  // Cell = the square [-R, R]^2 cut by the half-planes x . q_t <= |q_t|^2 / 2 (the bisectors
+  // with the projected neighbours). The origin lies strictly inside every constraint, so the
+  // cell is star-shaped about it and its area is the sum over its edges of
+  // (1/2) x (distance of the edge's line from the origin) x (edge length). Each line's edge is
+  // the interval of the line that the other constraints leave: with x = f + s tau (f the foot
+  // of the perpendicular from the origin, tau = (-n_y, n_x)), a constraint n_u . x <= b_u bounds
+  // s from one side, and the edge contributes b_t (s_max - s_min) / 2. A line repeated exactly
+  // (a repeated neighbour) counts once; a coincident neighbour (q = 0) bounds nothing. All
+  // loops are unrolled to the compile-time maximum, so the lines stay in registers.
+  constexpr int kLines = kMaxK + 4;  // neighbour bisectors, then the square's 4 edges
+  auto line_of = [&](int t, double& nx, double& ny, double& b) {
+    if (t < kMaxK) {
+      nx = t < m ? qx[t] : 0.0;
+      ny = t < m ? qy[t] : 0.0;
+      b = 0.5 * (nx * nx + ny * ny);  // 0: no constraint
+    } else {
+      const int e = t - kMaxK;
+      nx = e == 0 ? 1.0 : (e == 1 ? -1.0 : 0.0);
+      ny = e == 2 ? 1.0 : (e == 3 ? -1.0 : 0.0);
+      b = R;
+    }
+  };
+  double s2 = 0.0;  // twice the area
+#pragma unroll
+  for (int t = 0; t < kLines; ++t) {
+    double ax, ay, bt;
+    line_of(t, ax, ay, bt);
+    if (bt == 0.0) continue;
+    const double l2 = ax * ax + ay * ay;
+    const double fx = ax * bt / l2, fy = ay * bt / l2;
+    const double tx = -ay, ty = ax;
+    double smin = -INFINITY, smax = INFINITY;
+    bool empty = false;
+#pragma unroll
+    for (int u = 0; u < kLines; ++u) {
+      if (u == t) continue;
+      double nx, ny, bu;
+      line_of(u, nx, ny, bu);
+      if (bu == 0.0 || empty) continue;
+      if (nx == ax && ny == ay && bu == bt) {
+        if (u < t) empty = true;  // the same line: only its first copy has an edge
+        continue;
       }
-      if (((s1 < 0.0 && s2 > 0.0) || (s1 > 0.0 && s2 < 0.0)) && out < kMaxV) {
-        const double f = s1 / (s1 - s2);
-        vx[nxt][out] = vx[cur][v] + f * (vx[cur][v2] - vx[cur][v]);
-        vy[nxt][out] = vy[cur][v] + f * (vy[cur][v2] - vy[cur][v]);
-        ++out;
+      const double den = tx * nx + ty * ny;
+      const double num = bu - (fx * nx + fy * ny);
+      if (den > 0.0) {
+        smax = fmin(smax, num / den);
+      } else if (den < 0.0) {
+        smin = fmax(smin, num / den);
+      } else if (num < 0.0) {
+        empty = true;  // parallel and outside
       }
     }
-    nvtx = out;
-    cur = nxt;
+    if (!empty && smax > smin) s2 += bt * (smax - smin);
   }
-  double s = 0.0;
-  for (int v = 0; v < nvtx; ++v) {
-    const int v2 = v + 1 == nvtx ? 0 : v + 1;
-    s += vx[cur][v] * vy[cur][v2] - vx[cur][v2] * vy[cur][v];
-  }
-  area[i] = (float)(0.5 * fabs(s));
+  area[i] = (float)(0.5 * s2);
 }
 
 // Kernel radius of Sec. 5.2 "Poisson Kernels": the mean of the k nearest-neighbour distances
