@@ -5,9 +5,12 @@
 // Grid build: bounding box (deterministic two-stage min/max), cell size from the box
 // volume with at most ~8 cells per reference point, counting sort of the reference points
 // by cell (atomic cursors; the order inside a cell is arbitrary, which is harmless because
-// candidates are ranked by the pair (squared distance, index)). Query: one thread per query
-// walks Chebyshev rings of cells around its own cell and keeps the k best candidates in
-// registers; it stops once the k-th best distance is below the distance to the next ring.
+// candidates are ranked by the pair (squared distance, index)). Query: Chebyshev rings of
+// cells around the query's own cell, a row of cells (one contiguous range of the sorted
+// points) at a time, keeping the k best candidates in registers, until the k-th best
+// distance is below the distance to the next ring. One thread per query takes rings 0..3;
+// the few queries still unfinished (isolated points) are then searched by a wavefront each
+// (k_knn, k_knn_wave).
 #include <cfloat>
 #include <climits>
 #include <cmath>
