@@ -476,12 +476,14 @@ int choose_split(int64_t n_src, int64_t n_qry, int requested) {
   const int64_t qblocks = cdiv(n_qry, kQBlock);
   // Aim for >= 32768 blocks (128 per CU, ~25 rounds of resident blocks) while every split keeps
   // >= 8 tiles: blocks differ in cost (near tiles take the longer path), and the last round of
-  // a launch with few rounds leaves CUs idle. Measured at 1M x 1M: 2 splits 599 ms, 6 splits
-  // 556 ms, 16 splits 550 ms, 24 splits 549 ms; the automatic choice stops at 16 splits, which
-  // bounds the partial sums at 16 x 28 B per query.
+  // a launch with few rounds leaves CUs idle. Measured: 1M x 1M 2 splits 599 ms, 6 splits
+  // 556 ms, 16 splits 550 ms; 100K x 100K 16 splits 6.14 ms, 48 splits 5.70 ms. The partial
+  // sums (28 B per query and split) are held to kAutoSplitBytes, or 16 splits if that is more.
   int64_t s = cdiv(32768, qblocks);
   s = std::min<int64_t>(s, std::max<int64_t>(1, ntiles / 8));
-  s = std::max<int64_t>(1, std::min<int64_t>(s, kAutoSplit));
+  const int64_t mem_cap =
+      std::max<int64_t>(16, (int64_t)(kAutoSplitBytes / ((int64_t)kNAcc * 4 * qblocks * kQBlock)));
+  s = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(s, mem_cap), kMaxSplit));
   return (int)s;
 }
 

@@ -32,7 +32,7 @@ constexpr int kQpt = 2;        // queries held in registers per thread
 constexpr int kQBlock = kBlock * kQpt;  // queries per block
 constexpr int kNAcc = 7;       // per-query accumulators with the gradient: w, A[3], B[3]
 constexpr int kMaxSplit = 64;   // largest source split a caller may request
-constexpr int kAutoSplit = 16;  // largest split chosen automatically
+constexpr int64_t kAutoSplitBytes = int64_t(512) << 20;  // partial sums of an automatic split
 constexpr int kRedBlock = 256;  // threads per block for O(n) epilogue / reductions
 constexpr int kMaxK = 16;       // largest k for the kNN kernels
 

@@ -42,7 +42,10 @@ def test_workspace_bytes():
     a = dwg.workspace_bytes(1000, 1000)
     b = dwg.workspace_bytes(100_000, 100_000)
     assert 0 < a < b
-    assert b < 200 * 100_000 * 8  # O(n) bytes
+    # O(n) bytes: the all-pairs split partial sums are held to 512 MiB (or 16 splits), the
+    # rest is a few hundred bytes per point
+    assert b < (512 << 20) + 1000 * 100_000
+    assert dwg.workspace_bytes(4_000_000, 4_000_000) < 16 * 28 * 4_000_000 + 2000 * 4_000_000
     # invalid kernel parameters make it report 0
     assert dwg.workspace_bytes(1000, 1000, dwg.Params(lam=-1.0)) == 0
 
