@@ -663,8 +663,8 @@ __global__ __launch_bounds__(128) void k_voronoi_area(const float* __restrict__ 
   // the interval of the line that the other constraints leave: with x = f + s tau (f the foot
   // of the perpendicular from the origin, tau = (-n_y, n_x)), a constraint n_u . x <= b_u bounds
   // s from one side, and the edge contributes b_t (s_max - s_min) / 2. A line repeated exactly
-  // (a repeated neighbour) counts once; a coincident neighbour (q = 0) bounds nothing. All
-  // loops are unrolled to the compile-time maximum, so the lines stay in registers.
+  // (a repeated neighbour) counts once; a coincident neighbour (q = 0) bounds nothing. The
+  // loops run to the compile-time maximum, so the lines stay in registers.
   constexpr int kLines = kMaxK + 4;  // neighbour bisectors, then the square's 4 edges
   auto line_of = [&](int t, double& nx, double& ny, double& b) {
     if (t < kMaxK) {
@@ -679,8 +679,7 @@ __global__ __launch_bounds__(128) void k_voronoi_area(const float* __restrict__ 
     }
   };
   double s2 = 0.0;  // twice the area
-#pragma unroll
-  for (int t = 0; t < kLines; ++t) {
+  for (int t = 0; t < kLines; ++t) {  // (the inner loop is the unrolled one)
     double ax, ay, bt;
     line_of(t, ax, ay, bt);
     if (bt == 0.0) continue;
