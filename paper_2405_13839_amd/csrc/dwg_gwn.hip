@@ -49,6 +49,11 @@ __device__ __forceinline__ void tile_loop(const float4* sa, const float4* sb, co
 // go to FP32 partials, folded into running sums (Kahan-compensated when KAHAN). The
 // compensation terms live in LDS, one column per thread: they are touched once per tile, and
 // the 14 registers they would take hold the screened kernel at 4 waves per SIMD instead of 5.
+// Positions enter the pair arithmetic relative to the centre c of the block's query box and
+// scaled by kappa: kappa (x - c), formed when the tile is filled. The rounding of a near pair's
+// difference is then relative to the block's extent, not to |x| (kappa x rounded in FP32 would
+// move r by up to |x| 2^-24, enough to flip the clamp branch of pairs within ~1e-5 of r = delta
+// in a scene of size 2).
 template <int QPT, bool GRAD, bool SCREENED, bool KAHAN>
 __global__ __launch_bounds__(kBlock) void k_gwn(const float* __restrict__ Q, int64_t m,
                                                  const int32_t* __restrict__ qperm,
@@ -62,17 +67,18 @@ __global__ __launch_bounds__(kBlock) void k_gwn(const float* __restrict__ Q, int
   __shared__ float4 sb[kTile];
   const int tid = threadIdx.x;
   const int64_t q0 = (int64_t)blockIdx.x * (kBlock * QPT);
+  const float4 qlo = qbox[2 * blockIdx.x], qhi = qbox[2 * blockIdx.x + 1];
+  const float cx = 0.5f * (qlo.x + qhi.x), cy = 0.5f * (qlo.y + qhi.y), cz = 0.5f * (qlo.z + qhi.z);
   float qx[QPT], qy[QPT], qz[QPT];
 #pragma unroll
   for (int k = 0; k < QPT; ++k) {
     int64_t qi = q0 + k * kBlock + tid;
     if (qi >= m) qi = m - 1;
     const int64_t o = qperm[qi];
-    qx[k] = kappa * Q[o];
-    qy[k] = kappa * Q[m + o];
-    qz[k] = kappa * Q[2 * m + o];
+    qx[k] = kappa * (Q[o] - cx);
+    qy[k] = kappa * (Q[m + o] - cy);
+    qz[k] = kappa * (Q[2 * m + o] - cz);
   }
-  const float4 qlo = qbox[2 * blockIdx.x], qhi = qbox[2 * blockIdx.x + 1];
   __shared__ float cmp[KAHAN ? QPT * NA : 1][kBlock];  // thread-private columns
   float sum[QPT][NA];
 #pragma unroll
@@ -87,7 +93,10 @@ __global__ __launch_bounds__(kBlock) void k_gwn(const float* __restrict__ Q, int
   const int64_t t1 = min(t0 + tiles_per_split, ntiles);
   for (int64_t t = t0; t < t1; ++t) {
     __syncthreads();
-    sa[tid] = src[2 * (t * kTile + tid)];
+    {
+      const float4 a = src[2 * (t * kTile + tid)];
+      sa[tid] = make_float4(kappa * (a.x - cx), kappa * (a.y - cy), kappa * (a.z - cz), a.w);
+    }
     sb[tid] = src[2 * (t * kTile + tid) + 1];
     const float4 tlo = tbox[2 * t], thi = tbox[2 * t + 1];
     const float gx = fmaxf(0.0f, fmaxf(qlo.x - thi.x, tlo.x - qhi.x));
@@ -129,8 +138,9 @@ __global__ __launch_bounds__(kBlock) void k_gwn(const float* __restrict__ Q, int
   }
 }
 
-// Stage the sources in spatial order: (kappa p, 1/(kappa max(delta,eps))) and m = a n / (4 pi)
-// (kappa = the position scale of the kernel, 1 when plain).
+// Stage the sources in spatial order: (p, 1/(kappa max(delta,eps))) and m = a n / (4 pi)
+// (kappa = the position scale of the kernel, 1 when plain; positions stay unscaled, the
+// evaluation kernels scale differences).
 // A NaN delta poisons the source's m so that the result is NaN as in the definition.
 __global__ void k_stage(const float* __restrict__ P, const float* __restrict__ N,
                         const float* __restrict__ A, const float* __restrict__ D, int64_t n,
@@ -147,7 +157,7 @@ __global__ void k_stage(const float* __restrict__ P, const float* __restrict__ N
     const float id = fl > 0.0f ? 1.0f / fl : INFINITY;
     k = A[o] * kInv4Pi;
     if (d != d) k = NAN;
-    a = make_float4(kappa * P[o], kappa * P[n + o], kappa * P[2 * n + o], id);
+    a = make_float4(P[o], P[n + o], P[2 * n + o], id);
     b = make_float4(k * N[o], k * N[n + o], k * N[2 * n + o], 0.0f);
   }
   src[2 * j] = a;
@@ -155,8 +165,9 @@ __global__ void k_stage(const float* __restrict__ P, const float* __restrict__ N
   kk[j] = k;
 }
 
-// Box of each source tile (real sources only) and its largest radius max(delta, eps).
-__global__ __launch_bounds__(kTile) void k_tile_box(const float4* __restrict__ src, int64_t n,
+// Box of each source tile (real sources only) and its largest radius max(delta, eps), in the
+// unscaled units of the positions (the staged 1/radius carries kappa).
+__global__ __launch_bounds__(kTile) void k_tile_box(const float4* __restrict__ src, int64_t n, float kappa,
                                                     float4* __restrict__ tbox) {
   __shared__ float lds[7][kTile];
   const int64_t j = (int64_t)blockIdx.x * kTile + threadIdx.x;
@@ -166,7 +177,7 @@ __global__ __launch_bounds__(kTile) void k_tile_box(const float4* __restrict__ s
     v[0] = v[3] = a.x;
     v[1] = v[4] = a.y;
     v[2] = v[5] = a.z;
-    v[6] = 1.0f / a.w;  // radius (0 when 1/radius is +inf)
+    v[6] = 1.0f / (kappa * a.w);  // radius (0 when 1/radius is +inf)
     if (!(v[6] == v[6])) v[6] = INFINITY;
   }
   for (int d = 0; d < 7; ++d) lds[d][threadIdx.x] = v[d];
@@ -184,9 +195,9 @@ __global__ __launch_bounds__(kTile) void k_tile_box(const float4* __restrict__ s
   }
 }
 
-// Box of each block of kQBlock sorted queries (scaled coordinates).
+// Box of each block of kQBlock sorted queries.
 __global__ __launch_bounds__(kBlock) void k_query_box(const float* __restrict__ Q, int64_t m,
-                                                      const int32_t* __restrict__ qperm, float kappa,
+                                                      const int32_t* __restrict__ qperm,
                                                       float4* __restrict__ qbox) {
   __shared__ float lds[6][kBlock];
   float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
@@ -194,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void k_query_box(const float* __restrict__ 
     int64_t qi = (int64_t)blockIdx.x * kQBlock + k * kBlock + threadIdx.x;
     if (qi >= m) qi = m - 1;  // the kernel evaluates the clamped query there as well
     const int64_t o = qperm[qi];
-    const float x = kappa * Q[o], y = kappa * Q[m + o], z = kappa * Q[2 * m + o];
+    const float x = Q[o], y = Q[m + o], z = Q[2 * m + o];
     v[0] = fminf(v[0], x);
     v[1] = fminf(v[1], y);
     v[2] = fminf(v[2], z);
@@ -518,7 +529,7 @@ dwg_status launch_stage(const float* P, const float* N, const float* area, const
   hipLaunchKernelGGL(k_stage, dim3((unsigned)cdiv(w.npad, 256)), dim3(256), 0, stream, P, N, area,
                      delta, n, w.npad, eps, kappa, w.perm_s, w.src, w.kk);
   DWG_TRY_LAUNCH();
-  hipLaunchKernelGGL(k_tile_box, dim3((unsigned)w.ntiles), dim3(kTile), 0, stream, w.src, n, w.tbox);
+  hipLaunchKernelGGL(k_tile_box, dim3((unsigned)w.ntiles), dim3(kTile), 0, stream, w.src, n, kappa, w.tbox);
   DWG_TRY_LAUNCH();
   return DWG_OK;
 }
@@ -532,7 +543,7 @@ dwg_status launch_order(const float* P, int64_t n, const float* delta, float eps
     if (s != DWG_OK) return s;
   }
   hipLaunchKernelGGL(k_query_box, dim3((unsigned)(w.mpad / kQBlock)), dim3(kBlock), 0, stream, Q, m, w.perm_q,
-                     kappa, w.qbox);
+                     w.qbox);
   DWG_TRY_LAUNCH();
   return DWG_OK;
 }

@@ -492,7 +492,6 @@ __global__ __launch_bounds__(256) void k_tree_eval(const float* __restrict__ Q, 
   const int64_t o = qperm[qi < m ? qi : m - 1];
   const float ux = Q[o], uy = Q[m + o], uz = Q[2 * m + o];
   const double dqx = ux, dqy = uy, dqz = uz;  // the opening test runs in unscaled FP64
-  const float qx = kappa * ux, qy = kappa * uy, qz = kappa * uz;  // the pairs in the staged (scaled) units
   const double dk = kappa;
   float sum[NA], cmp[NA], acc[NA];
 #pragma unroll
@@ -540,10 +539,12 @@ __global__ __launch_bounds__(256) void k_tree_eval(const float* __restrict__ Q, 
         for (int j = s0; j < s1; ++j) {
           const float4 a = src[2 * (int64_t)j], b = src[2 * (int64_t)j + 1];
           if (direct) {
+            // kappa (p - q) from the unscaled positions: rounded relative to |p - q|, not to |q|
             if (SCREENED)
-              pair_screened<GRAD, false>(a, b, qx, qy, qz, sk, acc);
+              pair_screened_d<GRAD, false>(kappa * (a.x - ux), kappa * (a.y - uy), kappa * (a.z - uz), a.w, b, sk,
+                                           acc);
             else
-              pair_plain<GRAD, false>(a, b, qx, qy, qz, acc);
+              pair_plain_d<GRAD, false>(a.x - ux, a.y - uy, a.z - uz, a.w, b, acc);
           }
         }
         if (++visits == kFoldLeaves) {
