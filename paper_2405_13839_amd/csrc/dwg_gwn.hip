@@ -55,7 +55,7 @@ __device__ __forceinline__ void tile_loop(const float4* sa, const float4* sb, co
 // move r by up to |x| 2^-24, enough to flip the clamp branch of pairs within ~1e-5 of r = delta
 // in a scene of size 2).
 template <int QPT, bool GRAD, bool SCREENED, bool KAHAN>
-__global__ __launch_bounds__(kBlock) void k_gwn(const float* __restrict__ Q, int64_t m,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_gwn(const float* __restrict__ Q, int64_t m,
                                                  const int32_t* __restrict__ qperm,
                                                  const float4* __restrict__ src, int64_t ntiles,
                                                  int64_t nfull, int64_t tiles_per_split,

@@ -101,6 +101,33 @@ def test_duplicate_sources(lam):
     assert e_g(host(g), g_ref, skip=flag) <= TOL_G
 
 
+@pytest.mark.parametrize("lam,beta", [(10.0, 0.0), (0.0, 0.0), (10.0, 2.3)])
+def test_offset_cloud_clamp_boundary(lam, beta):
+    """A cloud far from the origin (unit cube at 4096) with delta = 0.1 for every source: ~80
+    pairs lie within 1e-3 delta of their clamp radius. Scaling absolute positions by kappa in
+    FP32 would move r by up to ~4e-4 here and flip the clamp branch of some of them (an FP32
+    emulation counts 58 at lambda = 10); the kernels take kappa (p - q) from differences, so
+    only pairs within the oracle's 1e-6 delta flag band may differ."""
+    dwg = _dwg()
+    n = 2000
+    rng = np.random.default_rng(31)
+    P = (rng.random((3, n)) + 4096.0).astype(np.float32)
+    N = unit_rows(rng, n)
+    a = np.full(n, 1.0 / n, np.float32)
+    d = np.full(n, 0.1, np.float32)
+    Pc = cuda(P)
+    w, g = dwg.gwn(Pc, cuda(N), cuda(a), cuda(d), Pc, dwg.Params(lam=lam, beta=beta))
+    if beta > 0:
+        w_ref, g_ref, flag = oracle.tree_gwn(P, N, a, d, P, lam=lam, beta=beta)
+    else:
+        w_ref, g_ref, flag = oracle.gwn(P, N, a, d, P, lam=lam)
+    ok = flag == 0
+    assert ok.mean() > 0.99
+    ew, eg = e_w(host(w)[ok], w_ref[ok]), e_g(host(g)[:, ok], g_ref[:, ok])
+    print(f"[offset] lam={lam} beta={beta}: e_w={ew:.2e} e_g={eg:.2e} flagged={int((~ok).sum())}")
+    assert ew <= TOL_W and eg <= TOL_G
+
+
 def test_sphere_closed_form_on_gpu():
     """Screened GWN of a sphere with exact normals (closed form) evaluated by the kernel."""
     dwg = _dwg()
