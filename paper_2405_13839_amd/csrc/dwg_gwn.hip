@@ -3,14 +3,16 @@
 //
 // Data layout in HBM (all carved from the caller's workspace; "sorted" = the spatial order
 // of dwg_sort.hip, perm[i] = original index of sorted position i):
-//   src   [2*npad] float4  sorted sources: (p_j, 1/max(delta_j, eps)), (m_j, 0) with
+//   src   [2*npad] float4  sorted sources: (p_j, 1/(kappa max(delta_j, eps))), (m_j, 0) with
 //                          m_j = a_j n_j / (4 pi); padding sources are all zero, which makes
 //                          their contribution exactly zero in the general path.
 //   kk    [npad]           a_j / (4 pi) per sorted source (restaging after the update)
 //   tbox  [2*ntiles]       per source tile: (min xyz, max radius), (max xyz, 0)
-//   qbox  [2*nqblk]        per block of 1024 sorted queries: (min xyz, 0), (max xyz, 0)
+//   qbox  [2*nqblk]        per block of kQBlock sorted queries: (min xyz, 0), (max xyz, 0)
 //   part  [split][7][mpad] per-split partial sums of w, A, B per sorted query
 //   theta [m] double       angle between consecutive normals (degrees), sorted order
+// Positions and boxes are in the caller's units; kappa = s log2(e) for the screened kernel
+// (1 for the plain one) is applied to pair differences inside the kernels.
 // Queries are gathered from the caller's planar [3][m] array through the query permutation.
 #include <cmath>
 
@@ -48,7 +50,8 @@ __device__ __forceinline__ void tile_loop(const float4* sa, const float4* sb, co
 // clamped or coincident -- and then runs the shorter far-pair loop. Each tile's contributions
 // go to FP32 partials, folded into running sums (Kahan-compensated when KAHAN). The
 // compensation terms live in LDS, one column per thread: they are touched once per tile, and
-// the 14 registers they would take hold the screened kernel at 4 waves per SIMD instead of 5.
+// the 14 registers they would take hold the screened kernel at 4 waves per SIMD instead of 5
+// (the kernel asks for 5, which it fits without spills).
 // Positions enter the pair arithmetic relative to the centre c of the block's query box and
 // scaled by kappa: kappa (x - c), formed when the tile is filled. The rounding of a near pair's
 // difference is then relative to the block's extent, not to |x| (kappa x rounded in FP32 would
