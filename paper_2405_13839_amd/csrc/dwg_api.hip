@@ -139,7 +139,8 @@ dwg_status eval_prepare(const float* P, const float* N, const float* area, const
   carve_tree(c, n, tree_leaf(kp), kp.tree_beta, &es->tw);
   DWG_PROPAGATE(tree_build(P, area, delta, n, kp.eps, es->tw, es->wk.perm_s, st));
   if (!same) DWG_PROPAGATE(spatial_sort(Q, m, nullptr, 0.0f, es->wk.sort, es->wk.perm_q, st));
-  return launch_stage(P, N, area, delta, n, kp.eps, position_scale(kp), es->wk, st);
+  DWG_PROPAGATE(launch_stage(P, N, area, delta, n, kp.eps, position_scale(kp), es->wk, st));
+  return tree_stage_leaves(es->wk, es->tw, position_scale(kp), st);
 }
 
 // w (and grad) at the sorted queries into the per-query partials.

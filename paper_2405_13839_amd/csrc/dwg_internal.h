@@ -178,6 +178,10 @@ size_t carve_tree(Carver& c, int64_t n, int leaf, double beta, TreeWork* out);
 dwg_status tree_build(const float* P, const float* area, const float* delta, int64_t n, float eps,
                       const TreeWork& t, int32_t* perm, hipStream_t st);
 // Node moments from the staged sources of w (call after every restaging).
+// Octree mode: rewrites the staged source positions as kappa (p - c_leaf), relative to the
+// centre of the leaf that holds each source (after tree_build with areas and launch_stage;
+// the all-pairs kernels never read sources staged this way).
+dwg_status tree_stage_leaves(const GwnWork& w, const TreeWork& t, float kappa, hipStream_t st);
 dwg_status tree_moments(const GwnWork& w, const TreeWork& t, hipStream_t st);
 // Octree-approximated w (and grad) at the sorted queries of w into w.part (split 1).
 dwg_status tree_eval(const float* Q, int64_t m, const dwg_kernel_params& kp, bool grad, const GwnWork& w,

@@ -33,7 +33,8 @@
 // lanes that opened it, and otherwise jumps to skip. Every query thus sees exactly the
 // per-query decisions of the paper's depth-first traversal; node loads are wave-uniform.
 // The FP64 criterion |q - c.m|^2 > crit^2 decides (unscaled); the far dipole and the leaf
-// pairs use the FP32 pair arithmetic of the all-pairs kernel in its scaled coordinates.
+// pairs use the FP32 pair arithmetic of the all-pairs kernel in its scaled coordinates (leaf
+// pairs from positions staged relative to the leaf's centre).
 #include <cmath>
 
 #include "dwg_internal.h"
@@ -472,6 +473,27 @@ __device__ __forceinline__ void fold(float* sum, float* cmp, const float* acc) {
   }
 }
 
+// Leaf-relative staging of the source positions for the leaf pairs, in place: kappa (p_j - c)
+// with c the leaf's centre rounded to FP32, which the traversal also subtracts from the
+// query, so a near pair's difference is rounded relative to the leaf's neighbourhood, not to
+// |p|. Every sorted source lies in exactly one leaf (one writer per source); .w keeps the
+// staged 1/(kappa max(delta, eps)), and the moments beside it are untouched.
+__global__ void k_tree_leafpos(const int4* __restrict__ node, const int32_t* __restrict__ total_p, int64_t cap,
+                               const double4* __restrict__ geo, float4* __restrict__ src, int64_t n, float kappa) {
+  const int64_t total = node_count(total_p, cap);
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (int64_t)gridDim.x * blockDim.x) {
+    const int4 nd = node[k];
+    if (!(nd.w >> 8)) continue;
+    const double4 g = geo[k];
+    const float cx = (float)g.x, cy = (float)g.y, cz = (float)g.z;
+    const int64_t e = nd.y < n ? nd.y : n;
+    for (int64_t j = nd.x; j < e; ++j) {
+      const float4 a = src[2 * j];
+      src[2 * j] = make_float4(kappa * (a.x - cx), kappa * (a.y - cy), kappa * (a.z - cz), a.w);
+    }
+  }
+}
+
 // Traversal: one thread per sorted query, one node index per wavefront (see the file head).
 // Contributions are summed in FP32 into `acc` and folded into the (Kahan-compensated when
 // KAHAN) running sums after every kFoldLeaves leaf visits of the wavefront and at the end
@@ -535,16 +557,16 @@ __global__ __launch_bounds__(256) void k_tree_eval(const float* __restrict__ Q, 
         const int s0 = __builtin_amdgcn_readfirstlane(nd.x);
         int s1 = __builtin_amdgcn_readfirstlane(nd.y);
         if (s1 > n_src) s1 = (int)n_src;
+        // the query relative to the leaf's centre, as its sources are staged (k_tree_leafpos)
+        const float lx = kappa * (ux - (float)g.x), ly = kappa * (uy - (float)g.y), lz = kappa * (uz - (float)g.z);
 #pragma unroll 4
         for (int j = s0; j < s1; ++j) {
           const float4 a = src[2 * (int64_t)j], b = src[2 * (int64_t)j + 1];
           if (direct) {
-            // kappa (p - q) from the unscaled positions: rounded relative to |p - q|, not to |q|
             if (SCREENED)
-              pair_screened_d<GRAD, false>(kappa * (a.x - ux), kappa * (a.y - uy), kappa * (a.z - uz), a.w, b, sk,
-                                           acc);
+              pair_screened<GRAD, false>(a, b, lx, ly, lz, sk, acc);
             else
-              pair_plain_d<GRAD, false>(a.x - ux, a.y - uy, a.z - uz, a.w, b, acc);
+              pair_plain<GRAD, false>(a, b, lx, ly, lz, acc);
           }
         }
         if (++visits == kFoldLeaves) {
@@ -717,6 +739,13 @@ dwg_status tree_build(const float* P, const float* area, const float* delta, int
   DWG_TRY_LAUNCH();
   hipLaunchKernelGGL(k_tree_crit, dim3(grid_cap(t.cap)), dim3(256), 0, st, total, t.cap, t.beta, t.rbits, t.dbits,
                      t.geo);
+  DWG_TRY_LAUNCH();
+  return DWG_OK;
+}
+
+dwg_status tree_stage_leaves(const GwnWork& w, const TreeWork& t, float kappa, hipStream_t st) {
+  hipLaunchKernelGGL(k_tree_leafpos, dim3(grid_cap(t.cap)), dim3(256), 0, st, t.node, t.off + t.n, t.cap, t.geo, w.src,
+                     t.n, kappa);
   DWG_TRY_LAUNCH();
   return DWG_OK;
 }
