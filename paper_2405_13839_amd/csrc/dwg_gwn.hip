@@ -40,6 +40,19 @@ __device__ __forceinline__ void tile_loop(const float4* sa, const float4* sb, co
       else
         pair_plain<GRAD, FAR>(a, b, qx[q], qy[q], qz[q], acc[q]);
     }
+    if (FAR && SCREENED && GRAD) {
+      // Instruction order of one source against the QPT = 2 queries (scheduling only; the
+      // arithmetic is unchanged): the two LDS reads, the 12 VALU of both differences and r^2,
+      // both rsq, 8 VALU, both exp, then the rest. Left to itself the compiler issues the four
+      // rsq (and four exp) of the unrolled pair of sources back to back; this order measured
+      // 528-531 ms against 546-551 ms per 1M x 1M launch on two cards, and equal on a third.
+      __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);   // DS read
+      __builtin_amdgcn_sched_group_barrier(0x002, 12, 0);  // VALU
+      __builtin_amdgcn_sched_group_barrier(0x400, 2, 0);   // transcendental
+      __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);
+      __builtin_amdgcn_sched_group_barrier(0x400, 2, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 34, 0);
+    }
   }
 }
 
