@@ -2,8 +2,10 @@
 sphere (2K, plain), torus + 2 ellipsoids (100K and 1M, screened), superquadrics + thin
 plates (5M, plain and screened) and 20 ellipsoids / tori (15M, screened). All sources take
 part; a seeded sample of queries is evaluated on the GPU and recomputed one by one by the
-FP64 oracle. Inputs (points, random unit normals, anchor radius by scipy's cKDTree) come
-from the seeded generators, never from the GPU path. Prints e_w / e_g per configuration."""
+FP64 oracle; the 1M and 5M configurations are also run as full launches (every point a
+query) and compared on a seeded 10K-point subset. Inputs (points, random unit normals,
+anchor radius by scipy's cKDTree) come from the seeded generators, never from the GPU path.
+Prints e_w / e_g per configuration."""
 import numpy as np
 import pytest
 
@@ -51,15 +53,23 @@ def test_config_full_size_sampled(name, gen, lam, nq):
     assert ew <= TOL_W and eg <= TOL_G
 
 
-@pytest.mark.parametrize("lam", [0.0, 10.0], ids=["plain", "screened"])
-def test_thin_structures_full_launch_10k_subset(lam):
-    """The 5M superquadrics + thin plates configuration evaluated as the iteration does: every
-    point is a query of one launch (all query blocks, the library's default split), and w and
-    grad w of a seeded 10K-point subset are compared with the FP64 oracle. In this scene,
-    scaling absolute positions by kappa in FP32 would flip the clamp branch of a few near
-    pairs (e_g ~ 6e-2 at one query in 10K); the kernels take kappa (p - q) from differences."""
+FULL_LAUNCH = [
+    # name, generator, lambda
+    ("C3 torus+ellipsoids 1M screened", lambda: synth.torus_ellipsoids(1_000_000, seed=102), 10.0),
+    ("C4 superquadrics+plates 5M", lambda: synth.superquadrics_plates(5_000_000, seed=103), 0.0),
+    ("C4 superquadrics+plates 5M screened", lambda: synth.superquadrics_plates(5_000_000, seed=103), 10.0),
+]
+
+
+@pytest.mark.parametrize("name,gen,lam", FULL_LAUNCH, ids=[c[0] for c in FULL_LAUNCH])
+def test_full_launch_10k_subset(name, gen, lam):
+    """A configuration evaluated as the iteration does: every point is a query of one launch
+    (all query blocks, the library's default split), and w and grad w of a seeded 10K-point
+    subset are compared with the FP64 oracle. In the 5M scene, scaling absolute positions by
+    kappa in FP32 would flip the clamp branch of a few near pairs (e_g ~ 6e-2 at one query in
+    10K); the kernels take kappa (p - q) from differences."""
     from paper_2405_13839_amd import dwg
-    c = synth.superquadrics_plates(5_000_000, seed=103)
+    c = gen()
     rng = np.random.default_rng(17)
     N = unit_rows(rng, c.n)
     d = anchor_radius(c.P)
@@ -70,6 +80,6 @@ def test_thin_structures_full_launch_10k_subset(lam):
     del w, g, Pc
     w_ref, g_ref, flag = oracle.gwn(c.P, N, c.area, d, np.ascontiguousarray(c.P[:, sel]), lam=lam)
     ew, eg = e_w(wg, w_ref), e_g(gg, g_ref, skip=flag)
-    print(f"[accuracy] C4 full launch lambda={lam}: 10K-point subset e_w={ew:.2e} e_g={eg:.2e} "
+    print(f"[accuracy] {name} full launch: 10K-point subset e_w={ew:.2e} e_g={eg:.2e} "
           f"flagged={int(flag.sum())}")
     assert ew <= TOL_W and eg <= TOL_G
