@@ -3,7 +3,7 @@ nodes, the iso-value w_bar, the w_bar level set, a gradient per face from the cr
 and every face's gradient added to its k nearest input points, then normalised.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring). Plain NumPy, float64, loops over
-cells and tetrahedra; shares no code with the GPU library.
+cells; shares no code with the GPU library.
 
 Definitions (the readings are listed with the design notes):
   * grid: the cube of the octree (lo = per-axis minimum of the points, side = the largest
@@ -14,18 +14,35 @@ Definitions (the readings are listed with the design notes):
     every corner with the current normals; w_bar = the mean of w over the input points
     (iso='points', the abstract's wording) or over the corners (iso='corners', Eq. 6 over
     the grid nodes).
-  * level set: each cube is cut into 6 tetrahedra around its diagonal from corner (0,0,0)
-    to (1,1,1), one per order (a, b, c) of the axes: corners 0, e_a, e_a + e_b, 7 (corner
-    index = x + 2y + 4z; the orders are (x,y,z), (x,z,y), (y,x,z), (y,z,x), (z,x,y),
-    (z,y,x)). A corner is inside when w > w_bar. One inside (or one outside) vertex L gives
-    the triangle of the crossings on the edges from L to the other three, in tetrahedron
-    order; two inside vertices A < B with outside C < D give the quad e(A,C), e(A,D),
-    e(B,D), e(B,C), split into (e(A,C), e(A,D), e(B,D)) and (e(A,C), e(B,D), e(B,C)).
-    The crossing on edge (u, v) is p_u + (w_bar - w_u) / (w_v - w_u) (p_v - p_u).
-  * face gradient: the cross product (q1 - q0) x (q2 - q0), turned to point away from the
-    inside vertices of its tetrahedron (towards decreasing w, i.e. the outward normal; q1 and
-    q2 are swapped when it is turned, so triangles are wound outwards); faces are assigned
-    to the k nearest input points of their centroid.
+  * level set, Marching Cubes (the paper's method; Lorensen & Cline 1987), cube by cube.
+    Corner index k = x + 2y + 4z; a corner is above when w > w_bar; an edge (u, v), u < v,
+    is cut when exactly one end is above, at p_u + (w_bar - w_u) / (w_v - w_u) (p_v - p_u).
+    Edges are numbered 0..11 in the lexicographic order of (u, v). On every face of the
+    cube, walked counter-clockwise as seen from outside, each maximal run of above corners
+    gives one segment, from the cut edge where the walk enters the run to the cut edge
+    where it leaves it. A face whose two above corners are diagonal therefore gets two
+    segments, one cutting off each above corner (the ambiguous face is resolved by
+    separating the above corners; the rule depends on the face's four signs only, so the
+    two cubes sharing a face draw the same segments and the surface is closed). The
+    segments chain into closed loops on the cube's surface; a loop is written from its
+    smallest edge index on, loops in the order of that index, and each loop of L vertices
+    is cut into the fan of triangles (v_0, v_i, v_{i+1}), i = 1 .. L-2. The walking
+    direction winds every loop so that (q1 - q0) x (q2 - q0) points away from the above
+    corners (towards decreasing w: outwards for outward normals).
+    With at most four corners above, the loops are the polygons of Lorensen & Cline's
+    cases (each of their triangulations is one fan per loop); with more, the complement of
+    a case is not reused (that is what opens holes next to an ambiguous face), the same
+    face rule is applied instead.
+  * level set, marching tetrahedra (a named option, not the paper's): each cube is cut into
+    6 tetrahedra around its diagonal from corner 0 to corner 7, one per order (a, b, c) of
+    the axes: corners 0, e_a, e_a + e_b, 7 (orders (x,y,z), (x,z,y), (y,x,z), (y,z,x),
+    (z,x,y), (z,y,x)). One inside (or one outside) vertex L gives the triangle of the
+    crossings on the edges from L to the other three, in tetrahedron order; two inside
+    vertices A < B with outside C < D give the quad e(A,C), e(A,D), e(B,D), e(B,C), split
+    into (e(A,C), e(A,D), e(B,D)) and (e(A,C), e(B,D), e(B,C)), each turned to point away
+    from the inside vertices.
+  * face gradient: the cross product (q1 - q0) x (q2 - q0) of the triangle as wound above;
+    faces are assigned to the k nearest input points of their centroid.
   * update: n_j = normalize(sum of its faces' vectors); a point with no face, or a zero sum,
     keeps its normal.
 """
@@ -93,6 +110,90 @@ def corners(cells, lo, side, depth):
     return uniq, np.ascontiguousarray(pos), inv.reshape(-1, 8)
 
 
+# Corner k of a cube sits at offset (k & 1, (k >> 1) & 1, (k >> 2) & 1) cells.
+CORNER_OFFSET = np.array([[k & 1, (k >> 1) & 1, (k >> 2) & 1] for k in range(8)], np.float64)
+# The 12 cube edges (u, v), u < v, v = u plus one axis step, in lexicographic order.
+CUBE_EDGES = sorted((u, u | (1 << a)) for u in range(8) for a in range(3) if not (u >> a) & 1)
+EDGE_INDEX = {e: i for i, e in enumerate(CUBE_EDGES)}
+
+
+def _face_walks():
+    """The 6 faces' corners in counter-clockwise order about the outward face normal (found
+    geometrically: sorted by the angle around the face centre in a right-handed (u, v) frame
+    of the face plane, u x v = the outward normal)."""
+    walks = []
+    for axis in range(3):
+        for side in (0, 1):
+            f = np.zeros(3)
+            f[axis] = 2.0 * side - 1.0
+            cs = [k for k in range(8) if ((k >> axis) & 1) == side]
+            u = np.zeros(3)
+            u[(axis + 1) % 3] = 1.0
+            v = np.cross(f, u)
+            c = CORNER_OFFSET[cs].mean(axis=0)
+            ang = [np.arctan2((CORNER_OFFSET[k] - c) @ v, (CORNER_OFFSET[k] - c) @ u) for k in cs]
+            walks.append([cs[i] for i in np.argsort(ang)])
+    return walks
+
+
+FACE_WALKS = _face_walks()
+
+
+def _edge(a, b):
+    return EDGE_INDEX[(min(a, b), max(a, b))]
+
+
+def cube_loops(above):
+    """Loops of cut-edge indices for one cube with the corners above w_bar flagged in
+    `above` (8 bools): face segments, chained, each loop from its smallest edge on."""
+    nxt = {}
+    for walk in FACE_WALKS:
+        for i in range(4):
+            a, b = walk[i], walk[(i + 1) % 4]
+            if above[a] or not above[b]:
+                continue  # not where the walk enters a run of above corners
+            j = (i + 1) % 4
+            while above[walk[(j + 1) % 4]]:
+                j = (j + 1) % 4
+            nxt[_edge(a, b)] = _edge(walk[j], walk[(j + 1) % 4])
+    loops, seen = [], set()
+    for e in sorted(nxt):
+        if e in seen:
+            continue
+        loop, x = [e], nxt[e]
+        seen.add(e)
+        while x != e:
+            seen.add(x)
+            loop.append(x)
+            x = nxt[x]
+        loops.append(loop)
+    return loops
+
+
+def marching_cubes(cells, cidx, pos, w, iso):
+    """Triangles [F, 3, 3] (float64, wound away from w > iso) and face vectors [F, 3]."""
+    P = np.asarray(pos, np.float64).T
+    tris, vecs = [], []
+    for ci in range(len(cells)):
+        cw = np.asarray(w, np.float64)[cidx[ci]]
+        cp = P[cidx[ci]]
+        above = [bool(x > iso) for x in cw]
+        if all(above) or not any(above):
+            continue
+        for loop in cube_loops(above):
+            q = []
+            for e in loop:
+                u, v = CUBE_EDGES[e]
+                t = (iso - cw[u]) / (cw[v] - cw[u])
+                q.append(cp[u] + t * (cp[v] - cp[u]))
+            for i in range(1, len(q) - 1):
+                tris.append(np.stack([q[0], q[i], q[i + 1]]))
+                vecs.append(np.cross(q[i] - q[0], q[i + 1] - q[0]))
+    if not tris:
+        return np.zeros((0, 3, 3)), np.zeros((0, 3))
+    return np.array(tris), np.array(vecs)
+
+
 def marching_tets(cells, cidx, pos, w, iso):
     """Triangles [F, 3, 3] (float64) and oriented face vectors [F, 3]."""
     P = np.asarray(pos, np.float64).T
@@ -143,7 +244,18 @@ def _field(P, N, area, delta, Q, lam, eps, beta, leaf):
     return w
 
 
-def level_set(P, N, area, delta, lam=0.0, eps=0.0, depth=8, dilate=1, beta=0.0, leaf=32, iso="points"):
+def extract(cells, cidx, pos, w, iso, surface="cubes"):
+    """The w_bar level set by Marching Cubes (surface='cubes', the paper's) or by marching
+    tetrahedra (surface='tets')."""
+    if surface == "cubes":
+        return marching_cubes(cells, cidx, pos, w, iso)
+    if surface == "tets":
+        return marching_tets(cells, cidx, pos, w, iso)
+    raise ValueError(f"unknown surface {surface!r}")
+
+
+def level_set(P, N, area, delta, lam=0.0, eps=0.0, depth=8, dilate=1, beta=0.0, leaf=32, iso="points",
+              surface="cubes"):
     """(triangles [F,3,3], face vectors [F,3], w_bar, corner positions [3,m], corner w [m])."""
     cells, lo, side = grid_cells(P, depth, dilate)
     _, pos, cidx = corners(cells, lo, side, depth)
@@ -152,14 +264,15 @@ def level_set(P, N, area, delta, lam=0.0, eps=0.0, depth=8, dilate=1, beta=0.0, 
         iso = float(np.mean(_field(P, N, area, delta, P, lam, eps, beta, leaf)))
     else:
         iso = float(np.mean(w))
-    tris, vecs = marching_tets(cells, cidx, pos, w, iso)
+    tris, vecs = extract(cells, cidx, pos, w, iso, surface)
     return tris, vecs, iso, pos, w
 
 
-def update(P, N, area, delta, lam=0.0, eps=0.0, depth=8, dilate=1, k=10, beta=0.0, leaf=32, iso="points"):
+def update(P, N, area, delta, lam=0.0, eps=0.0, depth=8, dilate=1, k=10, beta=0.0, leaf=32, iso="points",
+           surface="cubes"):
     """One iteration of the paper's update: (N_new [3,n], iso, number of faces, faces per
     point [n])."""
-    tris, vecs, iso, _, _ = level_set(P, N, area, delta, lam, eps, depth, dilate, beta, leaf, iso)
+    tris, vecs, iso, _, _ = level_set(P, N, area, delta, lam, eps, depth, dilate, beta, leaf, iso, surface)
     N = np.asarray(N, np.float64)
     n = N.shape[1]
     acc = np.zeros((3, n))
