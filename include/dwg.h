@@ -151,6 +151,8 @@ typedef struct dwg_mc_params {
   int dilate;   /* rings of neighbour cells around the cells holding points, 0..2 */
   int k;        /* nearest input points per face, 1..16 (paper: 10) */
   int iso;      /* w_bar: 0 = mean of w over the input points, 1 = over the grid corners */
+  int surface;  /* level-set extraction: 0 = Marching Cubes (the paper's), 1 = marching
+                   tetrahedra (an option) */
 } dwg_mc_params;
 
 /*
@@ -160,12 +162,15 @@ typedef struct dwg_mc_params {
  * corners sit at lo + c * side / 2^depth. One iteration: w at every corner (all-pairs, or
  * octree mode when kp->tree_beta > 0) with the current normals; w_bar = the FP64 mean of w
  * over the input points (iso = 0; evaluated in the same launch) or over the corners
- * (iso = 1, Eq. 6 over the grid nodes); the w_bar level set by marching tetrahedra (each cube cut into 6 tetrahedra
- * around its (0,0,0)-(1,1,1) diagonal, a corner inside when w > w_bar); per face the cross
- * product of its edges turned away from the inside corners; each face's vector added to
- * its k nearest input points; n_i = normalize(sum), a point with no face (or a zero sum)
- * keeps its normal. The per-face sums use 64-bit fixed-point atomics, so results are
- * deterministic.
+ * (iso = 1, Eq. 6 over the grid nodes); the w_bar level set by Marching Cubes (a corner is
+ * above when w > w_bar; on every face each run of above corners is cut off by one segment,
+ * so a face whose above corners are diagonal separates them and the surface is closed; the
+ * segments of a cube chain into loops, each cut into a fan of triangles; at most 5 per
+ * cube), or by marching tetrahedra when surface = 1 (each cube cut into 6 tetrahedra around
+ * its (0,0,0)-(1,1,1) diagonal); per face the cross product (q1 - q0) x (q2 - q0), wound to
+ * point away from the above corners; each face's vector added to its k nearest input
+ * points; n_i = normalize(sum), a point with no face (or a zero sum) keeps its normal. The
+ * per-face sums use 64-bit fixed-point atomics, so results are deterministic.
  *
  * Workspace: dwg_mc_workspace_bytes(n, kp, mcp, cells) with the cell count `cells` from
  * dwg_mc_cells (cells = 0 gives the bytes dwg_mc_cells itself needs).

@@ -184,9 +184,10 @@ dwg_status check_mcp(const dwg_mc_params* mcp, int64_t n, McParams* out) {
   DWG_CHECK(mcp->dilate >= 0 && mcp->dilate <= 2, "dilate must be in [0, 2]");
   DWG_CHECK(mcp->k >= 1 && mcp->k <= kMaxK, "k must be in [1, %d]", kMaxK);
   DWG_CHECK(mcp->iso == 0 || mcp->iso == 1, "iso must be 0 (points) or 1 (grid corners)");
+  DWG_CHECK(mcp->surface == 0 || mcp->surface == 1, "surface must be 0 (Marching Cubes) or 1 (marching tetrahedra)");
   const int64_t w = 2 * mcp->dilate + 1;
   DWG_CHECK(n > mcp->k && n * w * w * w < (int64_t(1) << 31), "need k < n < 2^31 / (2 dilate + 1)^3");
-  *out = McParams{mcp->depth, mcp->dilate, mcp->k, mcp->iso == 0 ? 1 : 0};
+  *out = McParams{mcp->depth, mcp->dilate, mcp->k, mcp->iso == 0 ? 1 : 0, mcp->surface};
   return DWG_OK;
 }
 
@@ -194,7 +195,7 @@ size_t mc_bytes(int64_t n, const dwg_kernel_params& kp, const McParams& mp, int6
   Carver c(nullptr);
   carve_mc_grid(c, n, mp, nullptr);
   if (cells > 0) {
-    carve_mc_faces(c, n, cells, mp.k, nullptr);
+    carve_mc_faces(c, n, cells, mp, nullptr);
     c.used = align256(c.used + gwn_bytes(n, 8 * cells + (mp.iso_points ? n : 0), kp));
   }
   return c.used;
@@ -214,8 +215,8 @@ dwg_status mc_prepare(const float* P, const float* N, const float* area, const f
     set_error("workspace too small for %lld grid cells: %zu bytes given, %zu needed", (long long)C, ws_bytes, need);
     return DWG_E_WORKSPACE;
   }
-  DWG_CHECK(12 * C < (int64_t(1) << 31), "too many grid cells (%lld)", (long long)C);
-  carve_mc_faces(c, n, C, mp.k, w);
+  DWG_CHECK(mc_faces_per_cell(mp) * C < (int64_t(1) << 31), "too many grid cells (%lld)", (long long)C);
+  carve_mc_faces(c, n, C, mp, w);
   int64_t m = 0;
   DWG_PROPAGATE(mc_corners(mp, *w, &m, st));
   if (mp.iso_points) DWG_PROPAGATE(mc_append_points(P, n, *w, st));

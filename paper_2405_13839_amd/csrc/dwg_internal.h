@@ -210,6 +210,7 @@ struct McParams {
   int dilate;      // rings of neighbour cells added around the cells holding points
   int k;           // nearest points per face
   int iso_points;  // 1: w_bar = mean of w over the input points; 0: over the grid corners
+  int tets;        // 1: marching tetrahedra (option); 0: Marching Cubes (the paper's)
 };
 struct McWork {
   // grid phase (sized by n)
@@ -245,10 +246,13 @@ struct McWork {
   unsigned long long* acc; // [n][3] fixed-point face sums
   KnnWork knn;             // uniform grid over the points
   int64_t n = 0, kcap = 0, C = 0, m = 0, ld = 0, mcap = 0, fcap = 0, chunk = 0;
+  int tets = 0;            // extraction: 0 Marching Cubes, 1 marching tetrahedra
 };
 int64_t mc_key_cap(int64_t n, const McParams& mp);
 size_t carve_mc_grid(Carver& c, int64_t n, const McParams& mp, McWork* out);
-size_t carve_mc_faces(Carver& c, int64_t n, int64_t C, int k, McWork* w);
+// Faces a cell can produce: 5 by Marching Cubes, 12 by marching tetrahedra.
+int mc_faces_per_cell(const McParams& mp);
+size_t carve_mc_faces(Carver& c, int64_t n, int64_t C, const McParams& mp, McWork* w);
 dwg_status mc_cells(const float* P, int64_t n, const McParams& mp, const McWork& w, int64_t* C_host,
                     hipStream_t st);
 dwg_status mc_corners(const McParams& mp, McWork& w, int64_t* m_host, hipStream_t st);

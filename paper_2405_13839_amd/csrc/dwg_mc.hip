@@ -8,15 +8,25 @@
 // evaluated cells are the cells holding points grown by `dilate` rings (inside the cube),
 // sorted by Morton code; their corners are deduplicated (radix sort + scan) and placed at
 // lo + c * side / 2^depth (FP64, rounded once to FP32).
-// Level set. Each cube is cut into 6 tetrahedra around the diagonal from corner 0 to corner 7
-// (corner index x + 2y + 4z), one per order (a, b, c) of the axes: 0, e_a, e_a + e_b, 7, in
-// the order (x,y,z), (x,z,y), (y,x,z), (y,z,x), (z,x,y), (z,y,x). A corner is inside when
-// w > w_bar. One lone inside (or outside) vertex L: the triangle of the crossings on the
-// edges from L to the other three in tetrahedron order; two inside A < B, outside C < D: the
-// quad e(A,C), e(A,D), e(B,D), e(B,C) split into (e(A,C), e(A,D), e(B,D)) and (e(A,C),
-// e(B,D), e(B,C)). Crossing on (u, v): p_u + (w_bar - w_u) / (w_v - w_u) (p_v - p_u), FP64.
-// Face vector: (q1 - q0) x (q2 - q0) turned away from the tetrahedron's inside vertices
-// (q1 and q2 swapped when turned, so every triangle is wound outwards).
+// Level set: Marching Cubes (the paper's "standard Marching Cubes"). Corner index
+// x + 2y + 4z; a corner is above when w > w_bar; the case of a cube is the 8-bit mask of its
+// above corners. Its triangles come from a 256-case table that this file derives at compile
+// time from one face rule: every face, walked counter-clockwise as seen from outside,
+// contributes a segment per run of above corners, from the cut edge where the walk enters the
+// run to the cut edge where it leaves (so a face with its two above corners on a diagonal
+// separates them, and two cubes sharing a face draw the same segments: the surface is
+// closed); the segments chain into loops, each written from its lowest edge number (edges
+// numbered by their corner pair (u, v), u < v, in lexicographic order), loops in that order,
+// and cut into the fan (v0, vi, vi+1). That winding makes (q1 - q0) x (q2 - q0) point away
+// from the above corners. A vertex on edge (u, v): p_u + (w_bar - w_u) / (w_v - w_u)
+// (p_v - p_u), FP64. At most 5 triangles per cube.
+// Option (not the paper's): marching tetrahedra, each cube cut into 6 tetrahedra around
+// the diagonal from corner 0 to corner 7, one per order (a, b, c) of the axes: 0, e_a,
+// e_a + e_b, 7, in the order (x,y,z), (x,z,y), (y,x,z), (y,z,x), (z,x,y), (z,y,x). One lone
+// inside (or outside) vertex L: the triangle of the crossings on the edges from L to the
+// other three in tetrahedron order; two inside A < B, outside C < D: the quad e(A,C), e(A,D),
+// e(B,D), e(B,C) split into (e(A,C), e(A,D), e(B,D)) and (e(A,C), e(B,D), e(B,C)); each turned
+// away from the tetrahedron's inside vertices (q1 and q2 swapped when turned).
 // Scatter. The k nearest points of each face centroid (the uniform-grid kNN) receive the
 // face vector through 64-bit fixed-point atomic adds (scale 2^40 / (3 h^2), h = the cell
 // size; |components| <= 3 h^2): integer sums do not depend on the order of the atomics, so
@@ -191,6 +201,66 @@ __device__ int tet_faces(const Vec3* p, const double* w, double iso, Vec3 (*out)
   return nf;
 }
 
+// ---- Marching Cubes case table (built at compile time from the face rule above) ----
+constexpr int kMcMaxTri = 5;
+struct McTable {
+  uint8_t ntri[256];
+  uint8_t tri[256][3 * kMcMaxTri];  // edge numbers, three per triangle
+};
+// edge e joins corners kEdgeLo[e] < kEdgeHi[e]
+constexpr int kEdgeLo[12] = {0, 0, 0, 1, 1, 2, 2, 3, 4, 4, 5, 6};
+constexpr int kEdgeHi[12] = {1, 2, 4, 3, 5, 3, 6, 7, 5, 6, 7, 7};
+// the corners of each face, counter-clockwise as seen from outside the cube
+constexpr int kFaceCyc[6][4] = {{0, 4, 6, 2}, {1, 3, 7, 5}, {0, 1, 5, 4}, {2, 6, 7, 3}, {0, 2, 3, 1}, {4, 5, 7, 6}};
+
+constexpr int mc_edge(int a, int b) {
+  const int lo = a < b ? a : b, hi = a < b ? b : a;
+  for (int e = 0; e < 12; ++e)
+    if (kEdgeLo[e] == lo && kEdgeHi[e] == hi) return e;
+  return -1;
+}
+
+constexpr McTable make_mc_table() {
+  McTable t{};
+  for (int c = 0; c < 256; ++c) {
+    int next[12] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+    for (int f = 0; f < 6; ++f)
+      for (int i = 0; i < 4; ++i) {
+        const int a = kFaceCyc[f][i], b = kFaceCyc[f][(i + 1) & 3];
+        if (((c >> a) & 1) || !((c >> b) & 1)) continue;  // the walk enters a run at (a, b)
+        int j = (i + 1) & 3;
+        while ((c >> kFaceCyc[f][(j + 1) & 3]) & 1) j = (j + 1) & 3;
+        next[mc_edge(a, b)] = mc_edge(kFaceCyc[f][j], kFaceCyc[f][(j + 1) & 3]);
+      }
+    bool used[12] = {};
+    int nt = 0;
+    for (int e = 0; e < 12; ++e) {
+      if (next[e] < 0 || used[e]) continue;
+      int loop[12] = {}, len = 0;
+      for (int x = e; !used[x]; x = next[x]) {
+        used[x] = true;
+        loop[len++] = x;
+      }
+      for (int v = 1; v + 1 < len; ++v, ++nt) {
+        t.tri[c][3 * nt + 0] = (uint8_t)loop[0];
+        t.tri[c][3 * nt + 1] = (uint8_t)loop[v];
+        t.tri[c][3 * nt + 2] = (uint8_t)loop[v + 1];
+      }
+    }
+    t.ntri[c] = (uint8_t)nt;
+  }
+  return t;
+}
+constexpr McTable kMcHost = make_mc_table();
+static_assert(kMcHost.ntri[0] == 0 && kMcHost.ntri[255] == 0 && kMcHost.ntri[1] == 1, "table");
+constexpr int mc_max_tri() {
+  int m = 0;
+  for (int c = 0; c < 256; ++c) m = kMcHost.ntri[c] > m ? kMcHost.ntri[c] : m;
+  return m;
+}
+static_assert(mc_max_tri() == kMcMaxTri, "at most five triangles per cube");
+__constant__ McTable kMc = kMcHost;
+
 __device__ void load_cell(int64_t ci, const int32_t* __restrict__ cidx, const float* __restrict__ pos, int64_t ld,
                           const float* __restrict__ w, Vec3* p, double* wv) {
   for (int k = 0; k < 8; ++k) {
@@ -256,6 +326,66 @@ __global__ void k_mt_emit(int64_t C, const int32_t* __restrict__ cidx, const flo
             tri[9 * f + 3 * q + 1] = (float)out[s][q].y;
             tri[9 * f + 3 * q + 2] = (float)out[s][q].z;
           }
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ int mc_case(const double* wv, double iso) {
+  int c = 0;
+  for (int k = 0; k < 8; ++k) c |= (wv[k] > iso ? 1 : 0) << k;
+  return c;
+}
+
+__device__ __forceinline__ Vec3 mc_vertex(int e, const Vec3* p, const double* wv, double iso) {
+  const int u = kEdgeLo[e], v = kEdgeHi[e];
+  return lerp_cross(p[u], p[v], wv[u], wv[v], iso);
+}
+
+__global__ void k_mc_count(int64_t C, const int32_t* __restrict__ cidx, const float* __restrict__ w,
+                           const double* __restrict__ iso_p, int32_t* __restrict__ cnt) {
+  const double iso = *iso_p;
+  for (int64_t ci = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; ci < C; ci += (int64_t)gridDim.x * blockDim.x) {
+    double wv[8];
+    for (int k = 0; k < 8; ++k) wv[k] = w[cidx[8 * ci + k]];
+    cnt[ci] = kMc.ntri[mc_case(wv, iso)];
+  }
+}
+
+// Triangles of every cell at off[ci], in table order: centroids (planar [3][ldf]), face
+// vectors (q1 - q0) x (q2 - q0), and optionally the triangles ([F][9]: q0, q1, q2).
+__global__ void k_mc_emit(int64_t C, const int32_t* __restrict__ cidx, const float* __restrict__ pos, int64_t ld,
+                          const float* __restrict__ w, const double* __restrict__ iso_p,
+                          const int32_t* __restrict__ off, int64_t fcap, float* __restrict__ cen, int64_t ldf,
+                          float4* __restrict__ vec, float* __restrict__ tri, int64_t tcap) {
+  const double iso = *iso_p;
+  for (int64_t ci = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; ci < C; ci += (int64_t)gridDim.x * blockDim.x) {
+    Vec3 p[8];
+    double wv[8];
+    load_cell(ci, cidx, pos, ld, w, p, wv);
+    const int c = mc_case(wv, iso);
+    const int nt = kMc.ntri[c];
+    int64_t f = off[ci];
+    for (int s = 0; s < nt; ++s, ++f) {
+      if (f >= fcap) continue;
+      const Vec3 q0 = mc_vertex(kMc.tri[c][3 * s], p, wv, iso), q1 = mc_vertex(kMc.tri[c][3 * s + 1], p, wv, iso),
+                 q2 = mc_vertex(kMc.tri[c][3 * s + 2], p, wv, iso);
+      const double ux = q1.x - q0.x, uy = q1.y - q0.y, uz = q1.z - q0.z;
+      const double vx = q2.x - q0.x, vy = q2.y - q0.y, vz = q2.z - q0.z;
+      if (cen) {
+        cen[f] = (float)((q0.x + q1.x + q2.x) / 3.0);
+        cen[ldf + f] = (float)((q0.y + q1.y + q2.y) / 3.0);
+        cen[2 * ldf + f] = (float)((q0.z + q1.z + q2.z) / 3.0);
+      }
+      if (vec)
+        vec[f] = make_float4((float)(uy * vz - uz * vy), (float)(uz * vx - ux * vz), (float)(ux * vy - uy * vx), 0.0f);
+      if (tri && f < tcap) {
+        const Vec3 q[3] = {q0, q1, q2};
+        for (int k = 0; k < 3; ++k) {
+          tri[9 * f + 3 * k + 0] = (float)q[k].x;
+          tri[9 * f + 3 * k + 1] = (float)q[k].y;
+          tri[9 * f + 3 * k + 2] = (float)q[k].z;
+        }
       }
     }
   }
@@ -401,13 +531,17 @@ size_t carve_mc_grid(Carver& c, int64_t n, const McParams& mp, McWork* out) {
   return c.used - s0;
 }
 
-size_t carve_mc_faces(Carver& c, int64_t n, int64_t C, int k, McWork* w) {
+int mc_faces_per_cell(const McParams& mp) { return mp.tets ? 12 : kMcMaxTri; }
+
+size_t carve_mc_faces(Carver& c, int64_t n, int64_t C, const McParams& mp, McWork* w) {
   const size_t s0 = c.used;
+  const int k = mp.k;
   McWork t{};
   McWork* o = w ? w : &t;
   o->C = C;
+  o->tets = mp.tets;
   o->mcap = 8 * C;
-  o->fcap = 12 * C;
+  o->fcap = mc_faces_per_cell(mp) * C;
   o->chunk = std::min<int64_t>(std::max<int64_t>(o->fcap, 1), int64_t(1) << 20);
   o->ckey[0] = c.take<uint64_t>((size_t)(8 * C));
   o->ckey[1] = c.take<uint64_t>((size_t)(8 * C));
@@ -487,11 +621,19 @@ dwg_status mc_corners(const McParams& mp, McWork& w, int64_t* m_host, hipStream_
 }
 
 dwg_status mc_faces(const McWork& w, float* tri, int64_t tcap, int64_t* F_host, hipStream_t st) {
-  hipLaunchKernelGGL(k_mt_count, dim3(grid_of(w.C)), dim3(256), 0, st, w.C, w.cidx, w.pos, w.ld, w.wc, w.iso, w.fcnt);
+  if (w.tets)
+    hipLaunchKernelGGL(k_mt_count, dim3(grid_of(w.C)), dim3(256), 0, st, w.C, w.cidx, w.pos, w.ld, w.wc, w.iso,
+                       w.fcnt);
+  else
+    hipLaunchKernelGGL(k_mc_count, dim3(grid_of(w.C)), dim3(256), 0, st, w.C, w.cidx, w.wc, w.iso, w.fcnt);
   DWG_TRY_LAUNCH();
   DWG_PROPAGATE_INT(exclusive_scan(w.fcnt, w.C, w.fsums, st));
-  hipLaunchKernelGGL(k_mt_emit, dim3(grid_of(w.C)), dim3(256), 0, st, w.C, w.cidx, w.pos, w.ld, w.wc, w.iso, w.fcnt,
-                     w.fcap, w.cen, w.fcap, w.vec, tri, tcap);
+  if (w.tets)
+    hipLaunchKernelGGL(k_mt_emit, dim3(grid_of(w.C)), dim3(256), 0, st, w.C, w.cidx, w.pos, w.ld, w.wc, w.iso,
+                       w.fcnt, w.fcap, w.cen, w.fcap, w.vec, tri, tcap);
+  else
+    hipLaunchKernelGGL(k_mc_emit, dim3(grid_of(w.C)), dim3(256), 0, st, w.C, w.cidx, w.pos, w.ld, w.wc, w.iso,
+                       w.fcnt, w.fcap, w.cen, w.fcap, w.vec, tri, tcap);
   DWG_TRY_LAUNCH();
   int32_t F = 0;
   DWG_TRY_HIP(hipMemcpyAsync(&F, w.fcnt + w.C, sizeof(int32_t), hipMemcpyDeviceToHost, st));

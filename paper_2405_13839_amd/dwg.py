@@ -41,7 +41,8 @@ class IterateParams(ctypes.Structure):
 
 
 class McParams(ctypes.Structure):
-    _fields_ = [("depth", ctypes.c_int), ("dilate", ctypes.c_int), ("k", ctypes.c_int), ("iso", ctypes.c_int)]
+    _fields_ = [("depth", ctypes.c_int), ("dilate", ctypes.c_int), ("k", ctypes.c_int), ("iso", ctypes.c_int),
+                ("surface", ctypes.c_int)]
 
 
 class IterStat(ctypes.Structure):
@@ -122,11 +123,13 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def _dev(t, name, dtype=torch.float32, shape=None):
+def _dev(t, name, dtype=torch.float32, shape=None, device=None):
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch tensor")
     if t.device.type != "cuda":
         raise ValueError(f"{name} must be on a ROCm device (got {t.device})")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} must be on {device} like the points (got {t.device})")
     if t.dtype != dtype:
         raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
     if not t.is_contiguous():
@@ -134,6 +137,21 @@ def _dev(t, name, dtype=torch.float32, shape=None):
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} must have shape {tuple(shape)} (got {tuple(t.shape)})")
     return t
+
+
+def _pts(t, name, device=None):
+    """A planar [3, n] float32 point array (x, y, z rows), n >= 1."""
+    t = _dev(t, name, device=device)
+    if t.dim() != 2 or t.shape[0] != 3 or t.shape[1] < 1:
+        raise ValueError(f"{name} must have shape (3, n) with n >= 1 (got {tuple(t.shape)})")
+    return t
+
+
+def _run(device, fn, *args):
+    """Calls the C entry point with `device` current: the library launches on the current
+    HIP device, the tensors' device."""
+    with torch.cuda.device(device):
+        return fn(*args)
 
 
 def _stream(device):
@@ -167,27 +185,28 @@ def gwn(P, N, area, delta, Q, params: Params | None = None, grad=True, ws=None, 
     """w [m] and (if grad) grad w [3, m] of the (screened) GWN of the oriented cloud at Q."""
     lib = load()
     params = params or Params()
-    P = _dev(P, "P")
+    P = _pts(P, "P")
     n = P.shape[1]
-    _dev(N, "N", shape=(3, n))
-    _dev(area, "area", shape=(n,))
-    if delta is not None:
-        _dev(delta, "delta", shape=(n,))
-    Q = _dev(Q, "Q")
-    m = Q.shape[1]
     dev = P.device
+    _dev(N, "N", shape=(3, n), device=dev)
+    _dev(area, "area", shape=(n,), device=dev)
+    if delta is not None:
+        _dev(delta, "delta", shape=(n,), device=dev)
+    Q = _pts(Q, "Q", device=dev)
+    m = Q.shape[1]
     if ws is None:
         ws = workspace(n, m, dev, params)
+    _dev(ws, "ws", dtype=torch.uint8, device=dev)
     w = torch.empty(m, dtype=torch.float32, device=dev)
     wm = torch.empty(1, dtype=torch.float64, device=dev) if want_wmean else None
     kp = params.c()
     if grad:
         g = torch.empty((3, m), dtype=torch.float32, device=dev)
-        _check(lib.dwg_gwn_grad(_ptr(P), _ptr(N), _ptr(area), _ptr(delta), n, _ptr(Q), m, ctypes.byref(kp), _ptr(w),
-                                _ptr(g), _ptr(wm), _ptr(ws), ws.numel(), _stream(dev)))
+        _check(_run(dev, lib.dwg_gwn_grad, _ptr(P), _ptr(N), _ptr(area), _ptr(delta), n, _ptr(Q), m, ctypes.byref(kp),
+            _ptr(w), _ptr(g), _ptr(wm), _ptr(ws), ws.numel(), _stream(dev)))
         return (w, g, wm) if want_wmean else (w, g)
-    _check(lib.dwg_gwn_eval(_ptr(P), _ptr(N), _ptr(area), _ptr(delta), n, _ptr(Q), m, ctypes.byref(kp), _ptr(w),
-                            _ptr(wm), _ptr(ws), ws.numel(), _stream(dev)))
+    _check(_run(dev, lib.dwg_gwn_eval, _ptr(P), _ptr(N), _ptr(area), _ptr(delta), n, _ptr(Q), m, ctypes.byref(kp),
+        _ptr(w), _ptr(wm), _ptr(ws), ws.numel(), _stream(dev)))
     return (w, wm) if want_wmean else w
 
 
@@ -197,21 +216,22 @@ def iterate(P, area, delta, N, params: Params | None = None, max_iters=50, fixed
     per iteration wmean, top-1% mean angle change (deg), mean chord, all-pairs kernel ms."""
     lib = load()
     params = params or Params()
-    P = _dev(P, "P")
+    P = _pts(P, "P")
     n = P.shape[1]
-    _dev(area, "area", shape=(n,))
+    _dev(area, "area", shape=(n,), device=P.device)
     if delta is not None:
-        _dev(delta, "delta", shape=(n,))
-    _dev(N, "N", shape=(3, n))
+        _dev(delta, "delta", shape=(n,), device=P.device)
+    _dev(N, "N", shape=(3, n), device=P.device)
     dev = P.device
     if ws is None:
         ws = workspace(n, n, dev, params)
+    _dev(ws, "ws", dtype=torch.uint8, device=dev)
     kp = params.c()
     ip = IterateParams(int(max_iters), int(bool(fixed_iters)), float(eps_deg), float(top_frac))
     stats = (IterStat * int(max_iters))()
     done = ctypes.c_int(0)
-    st = lib.dwg_iterate(_ptr(P), _ptr(area), _ptr(delta), n, _ptr(N), ctypes.byref(kp), ctypes.byref(ip), stats,
-                         ctypes.byref(done), _ptr(ws), ws.numel(), _stream(dev))
+    st = _run(dev, lib.dwg_iterate, _ptr(P), _ptr(area), _ptr(delta), n, _ptr(N), ctypes.byref(kp), ctypes.byref(ip),
+        stats, ctypes.byref(done), _ptr(ws), ws.numel(), _stream(dev))
     _check(st, ok=(DWG_OK, DWG_NOT_CONVERGED))
     out = torch.tensor([[s.wmean, s.top_mean_deg, s.mean_chord, s.gwn_ms] for s in stats[: done.value]],
                        dtype=torch.float64).reshape(-1, 4)
@@ -219,23 +239,30 @@ def iterate(P, area, delta, N, params: Params | None = None, max_iters=50, fixed
 
 
 def mc_workspace(P, params: Params | None = None, depth: int = 8, dilate: int = 1, k: int = 10,
-                 iso: str = "points") -> torch.Tensor:
+                 iso: str = "points", surface: str = "cubes") -> torch.Tensor:
     """Workspace for iterate_mc / level_set on P: sized for the actual number of grid cells."""
     lib = load()
-    P = _dev(P, "P")
+    P = _pts(P, "P")
     n = P.shape[1]
     kp = (params or Params()).c()
-    mp = McParams(int(depth), int(dilate), int(k), _iso(iso))
+    mp = McParams(int(depth), int(dilate), int(k), _iso(iso), _surface(surface))
     g = int(lib.dwg_mc_workspace_bytes(n, ctypes.byref(kp), ctypes.byref(mp), 0))
     if g == 0:
         raise DwgError(DWG_E_INVALID, "DWG_E_INVALID", "invalid level-set parameters")
     gws = torch.empty(g, dtype=torch.uint8, device=P.device)
     cells = ctypes.c_int64(0)
-    _check(lib.dwg_mc_cells(_ptr(P), n, ctypes.byref(mp), ctypes.byref(cells), _ptr(gws), gws.numel(),
-                            _stream(P.device)))
+    _check(_run(P.device, lib.dwg_mc_cells, _ptr(P), n, ctypes.byref(mp), ctypes.byref(cells), _ptr(gws), gws.numel(),
+        _stream(P.device)))
     del gws
     total = int(lib.dwg_mc_workspace_bytes(n, ctypes.byref(kp), ctypes.byref(mp), cells.value))
     return torch.empty(total, dtype=torch.uint8, device=P.device)
+
+
+def _surface(surface: str) -> int:
+    """'cubes' = Marching Cubes (the paper's extraction), 'tets' = marching tetrahedra."""
+    if surface not in ("cubes", "tets"):
+        raise ValueError("surface must be 'cubes' or 'tets'")
+    return 0 if surface == "cubes" else 1
 
 
 def _iso(iso: str) -> int:
@@ -245,52 +272,55 @@ def _iso(iso: str) -> int:
 
 
 def iterate_mc(P, area, delta, N, params: Params | None = None, depth=8, dilate=1, k=10, max_iters=50,
-               fixed_iters=False, eps_deg=0.1, top_frac=0.01, ws=None, iso: str = "points"):
+               fixed_iters=False, eps_deg=0.1, top_frac=0.01, ws=None, iso: str = "points", surface: str = "cubes"):
     """Algorithm 1 with the paper's level-set update, in place on N. Returns (status, stats
     float64 [T, 4]): per iteration w_bar (over the points, or the grid corners with
     iso='corners'), top-1% mean angle change, mean chord, evaluation ms."""
     lib = load()
     params = params or Params()
-    P = _dev(P, "P")
+    P = _pts(P, "P")
     n = P.shape[1]
-    _dev(area, "area", shape=(n,))
+    _dev(area, "area", shape=(n,), device=P.device)
     if delta is not None:
-        _dev(delta, "delta", shape=(n,))
-    _dev(N, "N", shape=(3, n))
+        _dev(delta, "delta", shape=(n,), device=P.device)
+    _dev(N, "N", shape=(3, n), device=P.device)
     if ws is None:
-        ws = mc_workspace(P, params, depth, dilate, k, iso)
+        ws = mc_workspace(P, params, depth, dilate, k, iso, surface)
+    _dev(ws, "ws", dtype=torch.uint8, device=P.device)
     kp = params.c()
-    mp = McParams(int(depth), int(dilate), int(k), _iso(iso))
+    mp = McParams(int(depth), int(dilate), int(k), _iso(iso), _surface(surface))
     ip = IterateParams(int(max_iters), int(bool(fixed_iters)), float(eps_deg), float(top_frac))
     stats = (IterStat * int(max_iters))()
     done = ctypes.c_int(0)
-    st = lib.dwg_iterate_mc(_ptr(P), _ptr(area), _ptr(delta), n, _ptr(N), ctypes.byref(kp), ctypes.byref(ip),
-                            ctypes.byref(mp), stats, ctypes.byref(done), _ptr(ws), ws.numel(), _stream(P.device))
+    st = _run(P.device, lib.dwg_iterate_mc, _ptr(P), _ptr(area), _ptr(delta), n, _ptr(N), ctypes.byref(kp),
+        ctypes.byref(ip), ctypes.byref(mp), stats, ctypes.byref(done), _ptr(ws), ws.numel(), _stream(P.device))
     _check(st, ok=(DWG_OK, DWG_NOT_CONVERGED))
     out = torch.tensor([[s.wmean, s.top_mean_deg, s.mean_chord, s.gwn_ms] for s in stats[: done.value]],
                        dtype=torch.float64).reshape(-1, 4)
     return st, out
 
 
-def level_set(P, N, area, delta, params: Params | None = None, depth=8, dilate=1, ws=None, iso: str = "points"):
+def level_set(P, N, area, delta, params: Params | None = None, depth=8, dilate=1, ws=None, iso: str = "points",
+              surface: str = "cubes"):
     """The w_bar level set: (triangles float32 [F, 3, 3] wound outwards, w_bar)."""
     lib = load()
     params = params or Params()
-    P = _dev(P, "P")
+    P = _pts(P, "P")
     n = P.shape[1]
     if ws is None:
-        ws = mc_workspace(P, params, depth, dilate, 10, iso)
+        ws = mc_workspace(P, params, depth, dilate, 10, iso, surface)
+    _dev(ws, "ws", dtype=torch.uint8, device=P.device)
     kp = params.c()
-    mp = McParams(int(depth), int(dilate), 10, _iso(iso))
+    mp = McParams(int(depth), int(dilate), 10, _iso(iso), _surface(surface))
     ntri = ctypes.c_int64(0)
     iso = ctypes.c_double(0.0)
     tri = torch.empty((1, 9), dtype=torch.float32, device=P.device)
     args = lambda t: (_ptr(P), _ptr(N), _ptr(area), _ptr(delta), n, ctypes.byref(kp), ctypes.byref(mp), _ptr(t),
                       t.shape[0], ctypes.byref(ntri), ctypes.byref(iso), _ptr(ws), ws.numel(), _stream(P.device))
-    st = lib.dwg_level_set(*args(tri))
+    st = _run(P.device, lib.dwg_level_set, *args(tri))
     if st == DWG_E_INVALID and ntri.value > 1:
         tri = torch.empty((ntri.value, 9), dtype=torch.float32, device=P.device)
-        st = lib.dwg_level_set(*args(tri))
+        st = _run(P.device, lib.dwg_level_set, *args(tri))
     _check(st)
     return tri[: ntri.value].reshape(-1, 3, 3), iso.value
 
@@ -298,33 +328,35 @@ def level_set(P, N, area, delta, params: Params | None = None, depth=8, dilate=1
 def random_normals(n: int, seed: int, device) -> torch.Tensor:
     lib = load()
     N = torch.empty((3, n), dtype=torch.float32, device=device)
-    _check(lib.dwg_init_normals(INIT_RANDOM, ctypes.c_uint64(seed), None, n, None, _ptr(N), None, 0,
-                                _stream(N.device)))
+    _check(_run(N.device, lib.dwg_init_normals, INIT_RANDOM, ctypes.c_uint64(seed), None, n, None, _ptr(N), None, 0,
+        _stream(N.device)))
     return N
 
 
 def voronoi_area(P, m: int = 15, ws=None) -> torch.Tensor:
     """Tangent-plane Voronoi area weights [n] (Sec. 5.1)."""
     lib = load()
-    P = _dev(P, "P")
+    P = _pts(P, "P")
     n = P.shape[1]
     if ws is None:
         ws = workspace(n, n, P.device)
+    _dev(ws, "ws", dtype=torch.uint8, device=P.device)
     out = torch.empty(n, dtype=torch.float32, device=P.device)
-    _check(lib.dwg_voronoi_area(_ptr(P), n, int(m), _ptr(out), _ptr(ws), ws.numel(), _stream(P.device)))
+    _check(_run(P.device, lib.dwg_voronoi_area, _ptr(P), n, int(m), _ptr(out), _ptr(ws), ws.numel(), _stream(P.device)))
     return out
 
 
 def delta_knn_window(P, k: int = 10, vmin: float = 0.0015, vmax: float = 0.015, ws=None) -> torch.Tensor:
     """The paper's windowed k-NN kernel radius [n] (Sec. 5.2)."""
     lib = load()
-    P = _dev(P, "P")
+    P = _pts(P, "P")
     n = P.shape[1]
     if ws is None:
         ws = workspace(n, n, P.device)
+    _dev(ws, "ws", dtype=torch.uint8, device=P.device)
     out = torch.empty(n, dtype=torch.float32, device=P.device)
-    _check(lib.dwg_delta_knn_window(_ptr(P), n, int(k), ctypes.c_float(vmin), ctypes.c_float(vmax), _ptr(out),
-                                    _ptr(ws), ws.numel(), _stream(P.device)))
+    _check(_run(P.device, lib.dwg_delta_knn_window, _ptr(P), n, int(k), ctypes.c_float(vmin), ctypes.c_float(vmax),
+        _ptr(out), _ptr(ws), ws.numel(), _stream(P.device)))
     return out
 
 
@@ -332,93 +364,99 @@ def octree(P, leaf: int = 0, ws=None):
     """Octree of the octree mode: (perm int32 [n], nodes int32 [count, 4] = (start, end,
     level, skip) in depth-first pre-order), both on P's device."""
     lib = load()
-    P = _dev(P, "P")
+    P = _pts(P, "P")
     n = P.shape[1]
     if ws is None:
         ws = workspace(n, n, P.device, Params(beta=2.3, leaf=leaf))
+    _dev(ws, "ws", dtype=torch.uint8, device=P.device)
     perm = torch.empty(n, dtype=torch.int32, device=P.device)
     cap = 2 * n
     nodes = torch.empty((cap, 4), dtype=torch.int32, device=P.device)
     cnt = ctypes.c_int64(0)
-    _check(lib.dwg_octree(_ptr(P), n, int(leaf), _ptr(perm), _ptr(nodes), cap, ctypes.byref(cnt), _ptr(ws),
-                          ws.numel(), _stream(P.device)))
+    _check(_run(P.device, lib.dwg_octree, _ptr(P), n, int(leaf), _ptr(perm), _ptr(nodes), cap, ctypes.byref(cnt),
+        _ptr(ws), ws.numel(), _stream(P.device)))
     return perm, nodes[:cnt.value]
 
 
 def pca_normals(P, ws=None) -> torch.Tensor:
     """Smallest-eigenvalue eigenvector of each point's 16-NN covariance, [3, n]."""
     lib = load()
-    P = _dev(P, "P")
+    P = _pts(P, "P")
     n = P.shape[1]
     if ws is None:
         ws = workspace(n, n, P.device)
+    _dev(ws, "ws", dtype=torch.uint8, device=P.device)
     N = torch.empty((3, n), dtype=torch.float32, device=P.device)
-    _check(lib.dwg_init_normals(INIT_PCA, ctypes.c_uint64(0), _ptr(P), n, None, _ptr(N), _ptr(ws), ws.numel(),
-                                _stream(P.device)))
+    _check(_run(P.device, lib.dwg_init_normals, INIT_PCA, ctypes.c_uint64(0), _ptr(P), n, None, _ptr(N), _ptr(ws),
+        ws.numel(), _stream(P.device)))
     return N
 
 
 def gauss_normals(P) -> torch.Tensor:
     """Gauss map p / |p|, [3, n]."""
     lib = load()
-    P = _dev(P, "P")
+    P = _pts(P, "P")
     n = P.shape[1]
     N = torch.empty((3, n), dtype=torch.float32, device=P.device)
-    _check(lib.dwg_init_normals(INIT_GAUSS, ctypes.c_uint64(0), _ptr(P), n, None, _ptr(N), None, 0,
-                                _stream(P.device)))
+    _check(_run(P.device, lib.dwg_init_normals, INIT_GAUSS, ctypes.c_uint64(0), _ptr(P), n, None, _ptr(N), None, 0,
+        _stream(P.device)))
     return N
 
 
 def mlp_normals(P, mlp_params, ws=None) -> torch.Tensor:
     lib = load()
-    P = _dev(P, "P")
+    P = _pts(P, "P")
     n = P.shape[1]
-    _dev(mlp_params, "mlp_params", shape=(mlp_param_count(),))
+    _dev(mlp_params, "mlp_params", shape=(mlp_param_count(),), device=P.device)
     if ws is None:
         ws = workspace(n, n, P.device)
+    _dev(ws, "ws", dtype=torch.uint8, device=P.device)
     N = torch.empty((3, n), dtype=torch.float32, device=P.device)
-    _check(lib.dwg_init_normals(INIT_MLP, ctypes.c_uint64(0), _ptr(P), n, _ptr(mlp_params), _ptr(N), _ptr(ws),
-                                ws.numel(), _stream(P.device)))
+    _check(_run(P.device, lib.dwg_init_normals, INIT_MLP, ctypes.c_uint64(0), _ptr(P), n, _ptr(mlp_params), _ptr(N),
+        _ptr(ws), ws.numel(), _stream(P.device)))
     return N
 
 
 def knn(R, Q, k: int, self_skip: bool = False, ws=None, want_dist=True):
     """(idx int32 [m, k], dist float32 [m, k]) of the k nearest points of R for each query."""
     lib = load()
-    R = _dev(R, "R")
-    Q = _dev(Q, "Q")
+    R = _pts(R, "R")
+    Q = _pts(Q, "Q", device=R.device)
     nr, m = R.shape[1], Q.shape[1]
     if ws is None:
         ws = workspace(nr, m, R.device)
+    _dev(ws, "ws", dtype=torch.uint8, device=R.device)
     idx = torch.empty((m, k), dtype=torch.int32, device=R.device)
     dist = torch.empty((m, k), dtype=torch.float32, device=R.device) if want_dist else None
-    _check(lib.dwg_knn(_ptr(R), nr, _ptr(Q), m, int(bool(self_skip)), int(k), _ptr(idx), _ptr(dist), _ptr(ws),
-                       ws.numel(), _stream(R.device)))
+    _check(_run(R.device, lib.dwg_knn, _ptr(R), nr, _ptr(Q), m, int(bool(self_skip)), int(k), _ptr(idx), _ptr(dist),
+        _ptr(ws), ws.numel(), _stream(R.device)))
     return idx, dist
 
 
 def delta_knn_mean(P, k: int = 10, scale: float = 1.0, ws=None) -> torch.Tensor:
     lib = load()
-    P = _dev(P, "P")
+    P = _pts(P, "P")
     n = P.shape[1]
     if ws is None:
         ws = workspace(n, n, P.device)
+    _dev(ws, "ws", dtype=torch.uint8, device=P.device)
     out = torch.empty(n, dtype=torch.float32, device=P.device)
-    _check(lib.dwg_delta_knn_mean(_ptr(P), n, int(k), float(scale), _ptr(out), _ptr(ws), ws.numel(),
-                                  _stream(P.device)))
+    _check(_run(P.device, lib.dwg_delta_knn_mean, _ptr(P), n, int(k), float(scale), _ptr(out), _ptr(ws), ws.numel(),
+        _stream(P.device)))
     return out
 
 
 def delta_anchor_mean(P, k: int = 10, n_anchor: int = 4096, scale: float = 1.0, ws=None) -> torch.Tensor:
     """scale x mean distance to the k nearest of ~n_anchor anchor points, [n]."""
     lib = load()
-    P = _dev(P, "P")
+    P = _pts(P, "P")
     n = P.shape[1]
     if ws is None:
         ws = workspace(n, n, P.device)
+    _dev(ws, "ws", dtype=torch.uint8, device=P.device)
     out = torch.empty(n, dtype=torch.float32, device=P.device)
-    _check(lib.dwg_delta_anchor_mean(_ptr(P), n, int(k), int(n_anchor), float(scale), _ptr(out), _ptr(ws),
-                                     ws.numel(), _stream(P.device)))
+    _check(_run(P.device, lib.dwg_delta_anchor_mean, _ptr(P), n, int(k), int(n_anchor), float(scale), _ptr(out),
+        _ptr(ws), ws.numel(), _stream(P.device)))
     return out
 
 
@@ -428,12 +466,14 @@ def mlp_param_count() -> int:
 
 def features(P, n_anchor: int = 4096, ws=None) -> torch.Tensor:
     lib = load()
-    P = _dev(P, "P")
+    P = _pts(P, "P")
     n = P.shape[1]
     if ws is None:
         ws = workspace(n, n, P.device)
+    _dev(ws, "ws", dtype=torch.uint8, device=P.device)
     out = torch.empty((n, MLP_IN), dtype=torch.float32, device=P.device)
-    _check(lib.dwg_features(_ptr(P), n, int(n_anchor), _ptr(out), _ptr(ws), ws.numel(), _stream(P.device)))
+    _check(_run(P.device, lib.dwg_features, _ptr(P), n, int(n_anchor), _ptr(out), _ptr(ws), ws.numel(),
+        _stream(P.device)))
     return out
 
 
@@ -441,11 +481,13 @@ def mlp_infer(params, X, ws=None) -> torch.Tensor:
     lib = load()
     X = _dev(X, "X")
     B = X.shape[0]
-    _dev(params, "params", shape=(mlp_param_count(),))
+    _dev(params, "params", shape=(mlp_param_count(),), device=X.device)
     if ws is None:
         ws = workspace(B, B, X.device)
+    _dev(ws, "ws", dtype=torch.uint8, device=X.device)
     Y = torch.empty((B, MLP_OUT), dtype=torch.float32, device=X.device)
-    _check(lib.dwg_mlp_infer(_ptr(params), _ptr(X), B, _ptr(Y), _ptr(ws), ws.numel(), _stream(X.device)))
+    _check(_run(X.device, lib.dwg_mlp_infer, _ptr(params), _ptr(X), B, _ptr(Y), _ptr(ws), ws.numel(),
+        _stream(X.device)))
     return Y
 
 
@@ -456,16 +498,17 @@ def mlp_train_step(params, adam_m, adam_v, step: int, lr: float, X, T, mask=None
     B = X.shape[0]
     npar = mlp_param_count()
     for t, nm in [(params, "params"), (adam_m, "adam_m"), (adam_v, "adam_v")]:
-        _dev(t, nm, shape=(npar,))
-    _dev(T, "T", shape=(B, 3))
+        _dev(t, nm, shape=(npar,), device=X.device)
+    _dev(T, "T", shape=(B, 3), device=X.device)
     if mask is not None:
-        _dev(mask, "mask", dtype=torch.uint8, shape=(B,))
+        _dev(mask, "mask", dtype=torch.uint8, shape=(B,), device=X.device)
     if ws is None:
         ws = workspace(B, B, X.device)
+    _dev(ws, "ws", dtype=torch.uint8, device=X.device)
     loss = torch.empty(1, dtype=torch.float32, device=X.device)
     grad = torch.empty(npar, dtype=torch.float32, device=X.device) if want_grad else None
-    _check(lib.dwg_mlp_train_step(_ptr(params), _ptr(adam_m), _ptr(adam_v), int(step), float(lr), _ptr(X), _ptr(T),
-                                  _ptr(mask), B, _ptr(grad), _ptr(loss), _ptr(ws), ws.numel(), _stream(X.device)))
+    _check(_run(X.device, lib.dwg_mlp_train_step, _ptr(params), _ptr(adam_m), _ptr(adam_v), int(step), float(lr),
+        _ptr(X), _ptr(T), _ptr(mask), B, _ptr(grad), _ptr(loss), _ptr(ws), ws.numel(), _stream(X.device)))
     return loss, grad
 
 

@@ -120,7 +120,8 @@ def test_octree_area_and_level_set_validation():
     kp = dwg.Params().c()
     ip = dwg.IterateParams(5, 0, 0.1, 0.01)
     for mp in [dwg.McParams(0, 1, 10, 0), dwg.McParams(17, 1, 10, 0), dwg.McParams(8, 3, 10, 0),
-               dwg.McParams(8, 1, 0, 0), dwg.McParams(8, 1, 17, 0), dwg.McParams(8, 1, 10, 2)]:
+               dwg.McParams(8, 1, 0, 0), dwg.McParams(8, 1, 17, 0), dwg.McParams(8, 1, 10, 2),
+               dwg.McParams(8, 1, 10, 0, 2), dwg.McParams(8, 1, 10, 0, -1)]:
         assert lib.dwg_mc_workspace_bytes(1000, ctypes.byref(kp), ctypes.byref(mp), 0) == 0
         done = ctypes.c_int(3)
         assert lib.dwg_iterate_mc(FAKE, FAKE, None, 1000, FAKE, ctypes.byref(kp), ctypes.byref(ip), ctypes.byref(mp),
@@ -129,6 +130,10 @@ def test_octree_area_and_level_set_validation():
     good = dwg.McParams(8, 1, 10, 0)
     g = lib.dwg_mc_workspace_bytes(1000, ctypes.byref(kp), ctypes.byref(good), 0)
     assert g > 0 and lib.dwg_mc_workspace_bytes(1000, ctypes.byref(kp), ctypes.byref(good), 500) > g
+    # marching tetrahedra keeps room for 12 faces per cell, Marching Cubes for 5
+    tets = dwg.McParams(8, 1, 10, 0, 1)
+    assert (lib.dwg_mc_workspace_bytes(1000, ctypes.byref(kp), ctypes.byref(tets), 500)
+            > lib.dwg_mc_workspace_bytes(1000, ctypes.byref(kp), ctypes.byref(good), 500))
     cells = ctypes.c_int64(9)
     assert lib.dwg_mc_cells(FAKE, 1000, ctypes.byref(good), ctypes.byref(cells), FAKE, 64, None) == dwg.DWG_E_WORKSPACE
     assert cells.value == 0

@@ -1,7 +1,7 @@
 """The paper's level-set update (Sec. 4.3, Algorithm 1) through the C ABI against oracle/mc.py:
-the extracted w_bar level set (triangles, iso-value, outward winding) and one update step of
-the normals, in all-pairs and octree mode. Inputs come from the seeded generators and the
-oracle only."""
+the extracted w_bar level set (Marching Cubes, the paper's; marching tetrahedra as the option:
+triangles, iso-value, outward winding) and one update step of the normals, in all-pairs and
+octree mode. Inputs come from the seeded generators and the oracle only."""
 import numpy as np
 import pytest
 import torch
@@ -19,14 +19,15 @@ def _dwg():
     return dwg
 
 
-@pytest.mark.parametrize("depth,dilate", [(5, 1), (6, 0)])
-def test_level_set_matches_oracle(depth, dilate):
+@pytest.mark.parametrize("depth,dilate,surface", [(5, 1, "cubes"), (6, 0, "cubes"), (5, 1, "tets")])
+def test_level_set_matches_oracle(depth, dilate, surface):
     from scipy.spatial import cKDTree
     dwg = _dwg()
     s = synth.sphere(3000, 0.002, 41)
-    tri, iso = dwg.level_set(cuda(s.P), cuda(s.N_true), cuda(s.area), None, dwg.Params(), depth, dilate)
+    tri, iso = dwg.level_set(cuda(s.P), cuda(s.N_true), cuda(s.area), None, dwg.Params(), depth, dilate,
+                             surface=surface)
     tri = host(tri).astype(np.float64)
-    otri, ovec, oiso, _, _ = mc.level_set(s.P, s.N_true, s.area, None, depth=depth, dilate=dilate)
+    otri, ovec, oiso, _, _ = mc.level_set(s.P, s.N_true, s.area, None, depth=depth, dilate=dilate, surface=surface)
     assert abs(iso - oiso) <= 1e-6
     assert abs(len(tri) - len(otri)) <= 0.002 * len(otri)
     cen, ocen = tri.mean(axis=1), otri.mean(axis=1)
@@ -41,8 +42,8 @@ def test_level_set_matches_oracle(depth, dilate):
     assert out > 0.97 and abs(out - oout) <= 0.002
 
 
-@pytest.mark.parametrize("beta", [0.0, 2.3])
-def test_mc_update_step_matches_oracle(beta):
+@pytest.mark.parametrize("beta,surface", [(0.0, "cubes"), (2.3, "cubes"), (2.3, "tets")])
+def test_mc_update_step_matches_oracle(beta, surface):
     dwg = _dwg()
     c = synth.torus_ellipsoids(8000, seed=4242)
     rng = np.random.default_rng(3)
@@ -50,11 +51,12 @@ def test_mc_update_step_matches_oracle(beta):
     d = oracle.anchor_delta(c.P).astype(np.float32)
     Nt = cuda(N0)
     st, stats = dwg.iterate_mc(cuda(c.P), cuda(c.area), cuda(d), Nt, dwg.Params(lam=10.0, beta=beta), depth=6,
-                               dilate=1, k=10, max_iters=1, fixed_iters=True)
-    N1, oiso, nf, cnt = mc.update(c.P, N0, c.area, d, lam=10.0, depth=6, dilate=1, k=10, beta=beta)
+                               dilate=1, k=10, max_iters=1, fixed_iters=True, surface=surface)
+    N1, oiso, nf, cnt = mc.update(c.P, N0, c.area, d, lam=10.0, depth=6, dilate=1, k=10, beta=beta,
+                                  surface=surface)
     assert abs(stats[0, 0].item() - oiso) <= 1e-5
     ang = angle_deg(host(Nt), N1)
-    print(f"[mc] beta={beta}: faces {nf}, angle p50 {np.median(ang):.2e} p99 {np.percentile(ang, 99):.2e} deg")
+    print(f"[mc] beta={beta} {surface}: faces {nf}, angle p50 {np.median(ang):.2e} p99 {np.percentile(ang, 99):.2e} deg")
     assert np.mean(ang <= 0.1) > 0.99 and np.median(ang) <= 1e-3
     keep = cnt == 0
     if keep.any():
