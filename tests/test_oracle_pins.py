@@ -44,6 +44,69 @@ def test_plain_sphere_surface_half(fib):
     np.testing.assert_allclose(w, pred, atol=1e-3)
 
 
+@pytest.mark.parametrize("dl", [0.05, 0.1, 0.2])
+def test_plain_sphere_surface_with_clamp(fib, dl):
+    """The clamped branch (Sec. 5.2, rho = max(r, delta_j)) on a sphere of radius R = 1 with
+    exact normals and a uniform radius delta: on the sphere the area inside chord r is
+    exactly pi r^2, so the clamp changes the surface value by
+    (1 / 4R) int_0^delta (r^3 / delta^3 - 1) dr = -3 delta / (16 R), and the self pair no
+    longer matters (the clamped integrand vanishes at r = 0): w = 1/2 - 3 delta / 16. A
+    dropped clamp misses by >= 0.009 here."""
+    D = np.full(fib.n, dl, np.float32)
+    Q = fib.P[:, :: fib.n // 64]
+    w, _, fl = oracle.gwn(fib.P, fib.N_true, fib.area, D, Q)
+    pred = 0.5 - 3.0 * float(np.float32(dl)) / 16.0
+    np.testing.assert_allclose(w, pred, atol=3e-4)
+    assert not fl.any()
+
+
+def test_clamp_uses_the_source_radius(fib):
+    """Two interleaved populations with radii d1 (even indices) and d2 (odd), each carrying
+    half of the sphere's area: every sample point sees both, so w = 1/2 - 3 (d1 + d2) / 32.
+    Taking the query's own radius instead would give 1/2 - 3 d_i / 16 (0.4906 or 0.4625
+    against 0.4766)."""
+    d1, d2 = 0.05, 0.2
+    D = np.where(np.arange(fib.n) % 2 == 0, d1, d2).astype(np.float32)
+    Q = fib.P[:, :: fib.n // 64]
+    w, _, _ = oracle.gwn(fib.P, fib.N_true, fib.area, D, Q)
+    np.testing.assert_allclose(w, 0.5 - 3.0 * (d1 + d2) / 32.0, atol=1e-3)
+
+
+@pytest.mark.parametrize("lam,dl", [(1.0, 0.1), (10.0, 0.05), (10.0, 0.2), (100.0, 0.2)])
+def test_screened_sphere_surface_with_clamp(fib, lam, dl):
+    """Screened kernel and clamp together (Eq. 5 with rho = max(r, delta)): phi uses the true
+    r and only r^3 is clamped, so on the sphere the surface value is the Yukawa double layer's
+    e^-x [(2 + x) sinh x - x cosh x] / (2x) (x = s R) plus
+    (1 / 4R) int_0^delta e^-sr (1 + sr) (r^3 / delta^3 - 1) dr (quadrature). Reading
+    phi(rho) instead moves it by 1.6e-3 at lambda = 100, delta = 0.2."""
+    from scipy.integrate import quad
+    s = math.sqrt(lam)
+    x = s
+    dd = float(np.float32(dl))
+    ws = math.exp(-x) * ((2 + x) * math.sinh(x) - x * math.cosh(x)) / (2 * x)
+    corr = quad(lambda r: math.exp(-s * r) * (1 + s * r) * (r ** 3 / dd ** 3 - 1), 0, dd, epsabs=1e-14)[0] / 4
+    D = np.full(fib.n, dl, np.float32)
+    Q = fib.P[:, :: fib.n // 64]
+    w, _, _ = oracle.gwn(fib.P, fib.N_true, fib.area, D, Q, lam=lam)
+    np.testing.assert_allclose(w, ws + corr, atol=3e-4 if dl < 0.1 else 1.5e-4)
+
+
+@pytest.mark.parametrize("lam", [0.0, 10.0])
+def test_radius_below_every_pair_distance_changes_nothing(lam):
+    """rho = max(r, delta_j): a radius below every pair's distance leaves every term, and so
+    w and grad w, bit for bit as without a radius."""
+    rng = np.random.default_rng(12)
+    P, N, a, _ = _rand_cloud(rng, 60)
+    Q = np.concatenate([P[:, :20], rng.uniform(-1, 1, (3, 20))], axis=1)
+    r = np.linalg.norm(P[:, None, :] - Q[:, :, None], axis=0)
+    dmin = r[r > 0].min()
+    D = np.full(P.shape[1], 0.5 * dmin)
+    w0, g0, _ = oracle.gwn(P, N, a, None, Q, lam=lam)
+    w1, g1, _ = oracle.gwn(P, N, a, D, Q, lam=lam)
+    np.testing.assert_array_equal(w0, w1)
+    np.testing.assert_array_equal(g0, g1)
+
+
 @pytest.mark.parametrize("lam", [1.0, 10.0, 100.0])
 def test_screened_sphere_closed_form(fib, lam):
     """Eq. 5 on a sphere of radius R = 1 (Yukawa double layer, x = s R, s = sqrt(lambda)):
@@ -249,9 +312,11 @@ def test_sphere_method_level():
     from random normals the iteration orients the sphere consistently (either global sign)."""
     c = synth.sphere(1500, 0.005, seed=100)
     P = c.P.astype(np.float64)
-    # kernel radius: twice the mean distance to the 10 nearest points (the build's default
-    # reading of the modified Poisson kernel's threshold)
-    delta = 2.0 * oracle.delta(P, 10)
+    # kernel radius: the anchor rule (mean distance to the 10 nearest anchors, every
+    # stride-th point) with 256 anchors, the resolution parameter for one convex solid; this
+    # gives delta = 0.25 R. The iteration orients the sphere from random normals once
+    # delta >~ R / 8 (512 anchors, delta = 0.16: yes; 1024 anchors, delta = 0.11: 77%).
+    delta = oracle.anchor_delta(c.P, k=10, n_anchor=256)
     N1, st = oracle.dwg_run(P, c.area, delta, c.N_true, max_iters=1)
     cos = np.sum(N1 * c.N_true, axis=0)
     assert np.all(cos > 0)
