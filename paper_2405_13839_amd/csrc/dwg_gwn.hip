@@ -65,11 +65,15 @@ __device__ __forceinline__ void tile_loop(const float4* sa, const float4* sb, co
 // compensation terms live in LDS, one column per thread: they are touched once per tile, and
 // the 14 registers they would take hold the screened kernel at 4 waves per SIMD instead of 5
 // (the kernel asks for 5, which it fits without spills).
-// Positions enter the pair arithmetic relative to the centre c of the block's query box and
-// scaled by kappa: kappa (x - c), formed when the tile is filled. The rounding of a near pair's
-// difference is then relative to the block's extent, not to |x| (kappa x rounded in FP32 would
-// move r by up to |x| 2^-24, enough to flip the clamp branch of pairs within ~1e-5 of r = delta
-// in a scene of size 2).
+// Positions enter the pair arithmetic relative to a point c of the block and scaled by kappa:
+// kappa (x - c), formed when the tile is filled. The rounding of a near pair's difference is
+// then relative to the pair's distance from c, not to |x| (kappa x rounded in FP32 would move
+// r by up to |x| 2^-24, enough to flip the clamp branch of pairs within ~1e-5 of r = delta in a
+// scene of size 2). c is the block's middle query (sorted position q0 + 256), not the centre
+// of its box: where the spatial order jumps inside a block (a lone point far from the rest of
+// its block), the box centre lies far from every query and all of the block's near pairs lose
+// precision; the middle query keeps the block's bulk exact relative to itself, and the far
+// query's pairs are long.
 template <int QPT, bool GRAD, bool SCREENED, bool KAHAN>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_gwn(const float* __restrict__ Q, int64_t m,
                                                  const int32_t* __restrict__ qperm,
@@ -84,7 +88,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
   const int tid = threadIdx.x;
   const int64_t q0 = (int64_t)blockIdx.x * (kBlock * QPT);
   const float4 qlo = qbox[2 * blockIdx.x], qhi = qbox[2 * blockIdx.x + 1];
-  const float cx = 0.5f * (qlo.x + qhi.x), cy = 0.5f * (qlo.y + qhi.y), cz = 0.5f * (qlo.z + qhi.z);
+  const int64_t oc = qperm[min(q0 + (kBlock * QPT) / 2, m - 1)];
+  const float cx = Q[oc], cy = Q[m + oc], cz = Q[2 * m + oc];
   float qx[QPT], qy[QPT], qz[QPT];
 #pragma unroll
   for (int k = 0; k < QPT; ++k) {

@@ -109,12 +109,12 @@ struct SortWork {
   float* part;      // [kBboxParts]
   float* box;       // [8]: bbox and the mean kernel radius
   double* rpart;    // [256] radius partial sums
-  uint32_t* key;    // [n]
-  int32_t* bins;    // [kSortBins + 1]
-  int32_t* cursor;  // [kSortBins]
-  int32_t* sums;    // scan tile totals
+  uint64_t* key[2]; // [n] radix-sort keys, ping-pong
+  int32_t* val;     // [n] indices (the second value buffer is the output permutation)
+  int32_t* hist;    // radix_hist_len(n)
+  int32_t* hsums;   // scan_sums_len(radix_hist_len(n))
 };
-constexpr int64_t kSortBins = int64_t(2) << 21;  // 2 radius classes x 2^21 Morton cells
+constexpr int kSortKeyBits = 22;  // radius class (1 bit) + Morton code of a 128^3 grid (21 bits)
 size_t carve_sort(Carver& c, int64_t n, SortWork* out);
 // perm[i] = original index of the i-th point in spatial order (deterministic).
 dwg_status spatial_sort(const float* P, int64_t n, const float* delta, float eps, const SortWork& w,

@@ -3,9 +3,10 @@
 // Sort key = (radius class, Morton code of the point's cell in a 128^3 grid over the bounding
 // box). Radius class 1 holds points whose kernel radius max(delta, eps) exceeds 4 x the mean
 // radius (outliers, sparse regions): grouped at the end, their large radii do not spoil the
-// near/far test of the tiles of dense surface points. Counting sort over 2 x 2^21 bins with
-// atomic cursors, then every bin's indices are put in ascending order, so the permutation does
-// not depend on the order in which atomics were served.
+// near/far test of the tiles of dense surface points. The (key, index) pairs go through the
+// stable LSD radix sort (3 passes of 8 bits over the 22-bit key): equal keys keep ascending
+// indices, so the permutation is deterministic, and the cost is linear in n whatever the
+// distribution (every point in one cell included).
 #include <cmath>
 
 #include "dwg_internal.h"
@@ -49,7 +50,7 @@ __global__ void k_radius_mean(const double* __restrict__ part, int nb, int64_t n
 }
 
 __global__ void k_sort_keys(const float* __restrict__ P, int64_t n, const float* __restrict__ D, float eps,
-                            const float* __restrict__ box, uint32_t* __restrict__ key, int32_t* __restrict__ bins) {
+                            const float* __restrict__ box, uint64_t* __restrict__ key, int32_t* __restrict__ val) {
   const float ox = box[0], oy = box[1], oz = box[2];
   const float ext = fmaxf(fmaxf(box[3] - ox, box[4] - oy), fmaxf(box[5] - oz, 1e-30f));
   const float sc = 128.0f / ext;
@@ -59,38 +60,8 @@ __global__ void k_sort_keys(const float* __restrict__ P, int64_t n, const float*
     const uint32_t cy = (uint32_t)min(max((int)((P[n + i] - oy) * sc), 0), 127);
     const uint32_t cz = (uint32_t)min(max((int)((P[2 * n + i] - oz) * sc), 0), 127);
     const uint32_t cls = radius_of(D, i, eps) > thr ? 1u : 0u;
-    const uint32_t k = (cls << 21) | (spread3(cx) << 2) | (spread3(cy) << 1) | spread3(cz);
-    key[i] = k;
-    atomicAdd(&bins[k], 1);
-  }
-}
-
-__global__ void k_zero(int32_t* __restrict__ a, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    a[i] = 0;
-}
-
-__global__ void k_sort_scatter(const uint32_t* __restrict__ key, int64_t n, const int32_t* __restrict__ start,
-                               int32_t* __restrict__ cursor, int32_t* __restrict__ perm) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t k = key[i];
-    perm[start[k] + atomicAdd(&cursor[k], 1)] = (int32_t)i;
-  }
-}
-
-// Ascending indices inside every bin (insertion sort; bins hold few points).
-__global__ void k_bin_sort(const int32_t* __restrict__ start, int64_t nbins, int32_t* __restrict__ perm) {
-  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nbins; b += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t s = start[b], e = start[b + 1];
-    for (int32_t i = s + 1; i < e; ++i) {
-      const int32_t v = perm[i];
-      int32_t j = i - 1;
-      while (j >= s && perm[j] > v) {
-        perm[j + 1] = perm[j];
-        --j;
-      }
-      perm[j + 1] = v;
-    }
+    key[i] = (uint64_t)((cls << 21) | (spread3(cx) << 2) | (spread3(cy) << 1) | spread3(cz));
+    val[i] = (int32_t)i;
   }
 }
 
@@ -104,10 +75,11 @@ size_t carve_sort(Carver& c, int64_t n, SortWork* out) {
   w.part = c.take<float>(kBboxParts);
   w.box = c.take<float>(8);
   w.rpart = c.take<double>(256);
-  w.key = c.take<uint32_t>((size_t)n);
-  w.bins = c.take<int32_t>((size_t)kSortBins + 1);
-  w.cursor = c.take<int32_t>((size_t)kSortBins);
-  w.sums = c.take<int32_t>(scan_sums_len(kSortBins));
+  w.key[0] = c.take<uint64_t>((size_t)n);
+  w.key[1] = c.take<uint64_t>((size_t)n);
+  w.val = c.take<int32_t>((size_t)n);
+  w.hist = c.take<int32_t>(radix_hist_len(n));
+  w.hsums = c.take<int32_t>(scan_sums_len((int64_t)radix_hist_len(n)));
   if (out) *out = w;
   return c.used - s0;
 }
@@ -118,18 +90,14 @@ dwg_status spatial_sort(const float* P, int64_t n, const float* delta, float eps
   if (s != DWG_OK) return s;
   hipLaunchKernelGGL(k_radius_partial, dim3(256), dim3(256), 0, st, delta, n, eps, w.rpart);
   hipLaunchKernelGGL(k_radius_mean, dim3(1), dim3(64), 0, st, w.rpart, 256, n, w.box);
-  hipLaunchKernelGGL(k_zero, dim3(grid_n(kSortBins + 1)), dim3(256), 0, st, w.bins, kSortBins + 1);
-  hipLaunchKernelGGL(k_zero, dim3(grid_n(kSortBins)), dim3(256), 0, st, w.cursor, kSortBins);
   DWG_TRY_LAUNCH();
-  hipLaunchKernelGGL(k_sort_keys, dim3(grid_n(n)), dim3(256), 0, st, P, n, delta, eps, w.box, w.key, w.bins);
+  hipLaunchKernelGGL(k_sort_keys, dim3(grid_n(n)), dim3(256), 0, st, P, n, delta, eps, w.box, w.key[0], w.val);
   DWG_TRY_LAUNCH();
-  s = exclusive_scan(w.bins, kSortBins, w.sums, st);
-  if (s != DWG_OK) return s;
-  hipLaunchKernelGGL(k_sort_scatter, dim3(grid_n(n)), dim3(256), 0, st, w.key, n, w.bins, w.cursor, perm);
-  DWG_TRY_LAUNCH();
-  hipLaunchKernelGGL(k_bin_sort, dim3(grid_n(kSortBins)), dim3(256), 0, st, w.bins, kSortBins, perm);
-  DWG_TRY_LAUNCH();
-  return DWG_OK;
+  // three passes (a 22-bit key) leave the sorted pairs in the second buffers: perm
+  static_assert((kSortKeyBits + 7) / 8 == 3, "an odd number of passes ends in the second buffers");
+  int32_t* const vals[2] = {w.val, perm};
+  int res = 0;
+  return radix_sort_pairs(w.key, vals, n, kSortKeyBits, w.hist, w.hsums, &res, st);
 }
 
 }  // namespace dwg

@@ -45,7 +45,7 @@ def angle_deg(a, b):
     return np.degrees(np.arctan2(cr, np.sum(a * b, axis=0)))
 
 
-def knn_radius(P, k=10, scale=2.0):
+def knn_radius(P, k=10, scale=1.0):
     """scale x mean distance to the k nearest other points, by scipy's cKDTree in float64
     (an input for both sides that does not come from the GPU path)."""
     from scipy.spatial import cKDTree
