@@ -304,7 +304,11 @@ dwg_status dwg_delta_anchor_mean(const float* P, int64_t n, int k, int64_t n_anc
 #define DWG_MLP_HID 128
 #define DWG_MLP_OUT 3
 #define DWG_FEAT_K 16
+/* Number of FP32 values in the parameter blob (the layout above). */
 int64_t dwg_mlp_param_count(void);
+/* Size in bytes of the parameter blob that dwg_init_normals (DWG_INIT_MLP), dwg_mlp_infer and
+ * dwg_mlp_train_step read: dwg_mlp_param_count() * sizeof(float). */
+size_t dwg_mlp_blob_bytes(void);
 
 /* Features [n][48] (float32) of every point; n_anchor >= 17. async. Workspace as for
  * dwg_delta_anchor_mean. */

@@ -1,6 +1,5 @@
 // C ABI entry points of libdwg: argument validation (always before the first HIP call),
 // workspace carving and the host-side iteration loop of Algorithm 1.
-#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -58,18 +57,13 @@ dwg_status check_kp(const dwg_kernel_params* kp) {
   return DWG_OK;
 }
 
-// 1 = gfx950, 0 = not yet checked, -1 = other architecture (per device ordinal).
-std::atomic<int> g_arch[64];
-
+// The current device must be a gfx950 (asked on every call: no state is kept).
 dwg_status check_device() {
   int dev = 0;
   DWG_TRY_HIP(hipGetDevice(&dev));
-  if (dev >= 0 && dev < 64 && g_arch[dev].load() != 0)
-    return g_arch[dev].load() > 0 ? DWG_OK : DWG_E_UNSUPPORTED;
   hipDeviceProp_t prop;
   DWG_TRY_HIP(hipGetDeviceProperties(&prop, dev));
   const bool ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
-  if (dev >= 0 && dev < 64) g_arch[dev].store(ok ? 1 : -1);
   if (!ok) {
     set_error("device %d is %s; libdwg is built for gfx950 only", dev, prop.gcnArchName);
     return DWG_E_UNSUPPORTED;
@@ -649,6 +643,8 @@ int64_t dwg_mlp_param_count(void) {
   return (int64_t)DWG_MLP_HID * DWG_MLP_IN + DWG_MLP_HID + (int64_t)DWG_MLP_HID * DWG_MLP_HID +
          DWG_MLP_HID + (int64_t)DWG_MLP_OUT * DWG_MLP_HID + DWG_MLP_OUT;
 }
+
+size_t dwg_mlp_blob_bytes(void) { return (size_t)dwg_mlp_param_count() * sizeof(float); }
 
 dwg_status dwg_features(const float* P, int64_t n, int64_t n_anchor, float* feat, void* ws,
                         size_t ws_bytes, void* stream) {

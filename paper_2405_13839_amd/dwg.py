@@ -78,6 +78,7 @@ def load():
     lib.dwg_delta_knn_mean.argtypes = [vp, i64, i32, f32, vp, vp, sz, vp]
     lib.dwg_delta_anchor_mean.argtypes = [vp, i64, i32, i64, f32, vp, vp, sz, vp]
     lib.dwg_mlp_param_count.restype = i64
+    lib.dwg_mlp_blob_bytes.restype = sz
     lib.dwg_octree.argtypes = [vp, i64, i32, vp, vp, i64, ctypes.POINTER(i64), vp, sz, vp]
     lib.dwg_delta_knn_window.argtypes = [vp, i64, i32, f32, f32, vp, vp, sz, vp]
     mcpp = ctypes.POINTER(McParams)
@@ -103,7 +104,7 @@ def load():
 
 EXPORTED = ["dwg_version", "dwg_status_string", "dwg_last_error", "dwg_workspace_bytes", "dwg_gwn_eval",
             "dwg_gwn_grad", "dwg_iterate", "dwg_init_normals", "dwg_knn", "dwg_delta_knn_mean",
-            "dwg_delta_anchor_mean", "dwg_mlp_param_count", "dwg_features", "dwg_mlp_infer",
+            "dwg_delta_anchor_mean", "dwg_mlp_param_count", "dwg_mlp_blob_bytes", "dwg_features", "dwg_mlp_infer",
             "dwg_mlp_train_step", "dwg_octree", "dwg_delta_knn_window", "dwg_voronoi_area", "dwg_mc_workspace_bytes",
             "dwg_mc_cells", "dwg_iterate_mc", "dwg_level_set"]
 
@@ -462,6 +463,10 @@ def delta_anchor_mean(P, k: int = 10, n_anchor: int = 4096, scale: float = 1.0, 
 
 def mlp_param_count() -> int:
     return int(load().dwg_mlp_param_count())
+
+
+def mlp_blob_bytes() -> int:
+    return int(load().dwg_mlp_blob_bytes())
 
 
 def features(P, n_anchor: int = 4096, ws=None) -> torch.Tensor:

@@ -103,6 +103,7 @@ def test_knn_and_mlp_validation():
                                   None) == dwg.DWG_E_INVALID
     assert lib.dwg_init_normals(7, 0, None, 10, None, FAKE, None, 0, None) == dwg.DWG_E_INVALID
     assert dwg.mlp_param_count() == 128 * 48 + 128 + 128 * 128 + 128 + 3 * 128 + 3
+    assert dwg.mlp_blob_bytes() == 4 * dwg.mlp_param_count()
 
 
 def test_octree_area_and_level_set_validation():
