@@ -5,11 +5,13 @@
 
 Configs (synth.CONFIGS): C1 sphere 2K, C2 torus + 2 ellipsoids 100K, C3 the same at 1M, C4 8
 superquadrics + 4 thin plates 5M, C5 10 ellipsoids + 10 tori 15M (`--n` overrides the size).
-Kernel radius: mean distance to the 10 nearest of `--anchors` anchor points (the scene's
-resolution parameter, like the paper's octree depth). Modes: `allpairs` (exact sum), `octree`
-(Sec. 5.2 traversal, beta 2.3), `mc` (the paper's level-set update on a grid of `--depth`,
-octree evaluation). Timing covers the radius, the initial normals and the iterations, with
-the points already on the GPU.
+Kernel radius (`--radius`): `anchor` = mean distance to the 10 nearest of `--anchors` anchor
+points (the scene's resolution parameter, like the paper's octree depth); `window` = the
+paper's rule (Sec. 5.2): the mean of the 10-NN distances inside [0.0015, 0.015] x the longest
+side of the bounding box (the paper's window in units of its models' size). Modes: `allpairs`
+(exact sum), `octree` (Sec. 5.2 traversal, beta 2.3), `mc` (the paper's level-set update on a
+grid of `--depth`, Marching Cubes unless `--surface tets`, octree evaluation). Timing covers
+the radius, the initial normals and the iterations, with the points already on the GPU.
 """
 from __future__ import annotations
 
@@ -31,6 +33,9 @@ def main(argv=None) -> int:
     ap.add_argument("--lam", type=float, default=10.0)
     ap.add_argument("--max-iters", type=int, default=100)
     ap.add_argument("--depth", type=int, default=8)
+    ap.add_argument("--radius", default="anchor", choices=["anchor", "window"])
+    ap.add_argument("--surface", default="cubes", choices=["cubes", "tets"])
+    ap.add_argument("--mc-k", type=int, default=10)
     args = ap.parse_args(argv)
     import torch
 
@@ -46,13 +51,17 @@ def main(argv=None) -> int:
     P, area = torch.from_numpy(c.P).to(dev), torch.from_numpy(c.area).to(dev)
     prm = dwg.Params(lam=args.lam, beta=0.0 if args.mode == "allpairs" else 2.3)
     ws = dwg.workspace(c.n, c.n, dev, prm)
-    mws = dwg.mc_workspace(P, prm, args.depth, 1, 10) if args.mode == "mc" else None
+    mws = dwg.mc_workspace(P, prm, args.depth, 1, args.mc_k, surface=args.surface) if args.mode == "mc" else None
+    side = float((P.max(dim=1).values - P.min(dim=1).values).max())
     mlp = None
     if args.init == "mlp":
         mlp = mlp_init.load_params(os.path.join(os.path.dirname(__file__), "weights", "mlp_init.safetensors"), dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    delta = dwg.delta_anchor_mean(P, 10, args.anchors, 1.0, ws=ws)
+    if args.radius == "anchor":
+        delta = dwg.delta_anchor_mean(P, 10, args.anchors, 1.0, ws=ws)
+    else:
+        delta = dwg.delta_knn_window(P, 10, 0.0015 * side, 0.015 * side, ws=ws)
     if args.init == "mlp":
         N = dwg.mlp_normals(P, mlp, ws=ws)
     elif args.init == "pca":
@@ -62,14 +71,16 @@ def main(argv=None) -> int:
     else:
         N = dwg.random_normals(c.n, 7, dev)
     if args.mode == "mc":
-        st, stats = dwg.iterate_mc(P, area, delta, N, prm, depth=args.depth, max_iters=args.max_iters, ws=mws)
+        st, stats = dwg.iterate_mc(P, area, delta, N, prm, depth=args.depth, k=args.mc_k, max_iters=args.max_iters,
+                                   ws=mws, surface=args.surface)
     else:
         st, stats = dwg.iterate(P, area, delta, N, prm, max_iters=args.max_iters, ws=ws)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     rep = metrics.orientation_report(N.cpu().numpy(), c.N_true, c.comp)
     print(json.dumps({"config": args.config, "n": c.n, "mode": args.mode, "init": args.init, "anchors": args.anchors,
-                      "lambda": args.lam, "converged": st == dwg.DWG_OK, "iterations": int(stats.shape[0]),
+                      "radius": args.radius, "surface": args.surface if args.mode == "mc" else None,
+                      "depth": args.depth if args.mode == "mc" else None, "lambda": args.lam, "converged": st == dwg.DWG_OK, "iterations": int(stats.shape[0]),
                       "seconds": dt, "eval_ms_median": float(stats[:, 3].median()),
                       "median_delta": float(delta.median()), "mae_deg": rep["mae_deg"], "agree": rep["agree"]}))
     return 0
