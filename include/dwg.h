@@ -119,6 +119,21 @@ dwg_status dwg_gwn_grad(const float* P, const float* N, const float* area, const
                         void* stream);
 
 /*
+ * dwg_gwn_grad_static -- dwg_gwn_grad without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc). Same arguments, outputs and errors as dwg_gwn_grad minus ws / ws_bytes.
+ * Scratch comes from a static device array of 64 MiB that each GPU holds from the first call
+ * on it until the process ends; the call itself allocates nothing. Calls with a scratch need
+ * above 64 MiB return DWG_E_INVALID (split = 0 halves the automatic source split until the
+ * need fits; for scale, n = m = 650,000 fits all-pairs, n = m = 170,000 in octree mode). All calls on one GPU share that array: calls
+ * that overlap in time on one GPU (several streams or threads) race and must be serialised by
+ * the caller. async. Results agree with dwg_gwn_grad to rounding (the split may differ).
+ */
+dwg_status dwg_gwn_grad_static(const float* P, const float* N, const float* area, const float* delta,
+                               int64_t n, const float* Q, int64_t m, const dwg_kernel_params* kp,
+                               float* w, float* grad, double* wmean, void* stream);
+
+/*
  * Octree mode (tree_beta > 0; Sec. 5.2 "Octree Traversal"). The sources are put in an
  * octree: root = the cube over their bounding box (side = the largest extent), cells down
  * to level 21 (Morton order of floor((x - lo) 2^21 / side), FP64), a node = a non-empty cell,

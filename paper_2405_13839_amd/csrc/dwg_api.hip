@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "dwg_internal.h"
 
@@ -228,6 +229,46 @@ dwg_status mc_field(const dwg_kernel_params& kp, const McParams& mp, const McWor
   return mc_point_iso(w, w.wc + w.m, w.n, st);
 }
 
+// ---- Scratch of dwg_gwn_grad_static: a device array instead of a caller workspace ----
+// `scratch` is a device symbol: on the host its name stands for a host-side shadow, so its
+// device address is asked from the runtime once per device (with that device current) and
+// kept; kernels and copies only ever get that address.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices];  // device address of `scratch` per device ordinal
+
+dwg_status static_scratch(void** out) {
+  int dev = 0;
+  DWG_TRY_HIP(hipGetDevice(&dev));
+  DWG_CHECK(dev >= 0 && dev < kMaxDevices, "device ordinal %d outside [0, %d)", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error("hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+      return DWG_E_DEVICE;
+    }
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return DWG_OK;
+}
+
+// The kernel parameters dwg_gwn_grad_static runs with: an automatic source split is halved
+// until the evaluation fits the static scratch (the split only groups the partial sums).
+dwg_kernel_params static_params(int64_t n, int64_t m, const dwg_kernel_params& kp) {
+  dwg_kernel_params k = kp;
+  if (!tree_mode(k) && k.split == 0) {
+    k.split = choose_split(n, m, 0);
+    while (k.split > 1 && gwn_bytes(n, m, k) > kStaticScratchBytes) k.split = (k.split + 1) / 2;
+  }
+  return k;
+}
+
 }  // namespace
 
 extern "C" {
@@ -270,6 +311,27 @@ dwg_status dwg_gwn_grad(const float* P, const float* N, const float* area, const
                         float* w, float* grad, double* wmean, void* ws, size_t ws_bytes,
                         void* stream) {
   return gwn_common(P, N, area, delta, n, Q, m, kp, true, w, grad, wmean, ws, ws_bytes, stream);
+}
+
+dwg_status dwg_gwn_grad_static(const float* P, const float* N, const float* area, const float* delta,
+                               int64_t n, const float* Q, int64_t m, const dwg_kernel_params* kpp,
+                               float* w, float* grad, double* wmean, void* stream) {
+  DWG_CHECK(P && N && area && Q, "P, N, area and Q must not be NULL");
+  DWG_CHECK(n >= 1 && m >= 1, "n and m must be >= 1 (got n=%lld, m=%lld)", (long long)n, (long long)m);
+  DWG_CHECK(n < (int64_t(1) << 31) && m < (int64_t(1) << 31), "n and m must be < 2^31 (int32 point indices)");
+  DWG_CHECK(grad != nullptr, "grad must not be NULL");
+  DWG_PROPAGATE(check_kp(kpp));
+  const dwg_kernel_params kp = static_params(n, m, kpp ? *kpp : kDefaultKp);
+  DWG_CHECK(!tree_mode(kp) || n < (int64_t(1) << 30), "octree mode needs n < 2^30");
+  const size_t need = gwn_bytes(n, m, kp);
+  DWG_CHECK(need <= kStaticScratchBytes,
+            "n = %lld sources and m = %lld queries need %zu bytes of scratch; the static scratch holds %zu "
+            "(use dwg_gwn_grad with a workspace)",
+            (long long)n, (long long)m, need, kStaticScratchBytes);
+  DWG_PROPAGATE(check_device());
+  void* ws = nullptr;
+  DWG_PROPAGATE(static_scratch(&ws));
+  return gwn_common(P, N, area, delta, n, Q, m, &kp, true, w, grad, wmean, ws, kStaticScratchBytes, stream);
 }
 
 dwg_status dwg_iterate(const float* P, const float* area, const float* delta, int64_t n,

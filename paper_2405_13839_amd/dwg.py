@@ -71,6 +71,7 @@ def load():
     lib.dwg_workspace_bytes.argtypes = [i64, i64, kpp]
     lib.dwg_gwn_eval.argtypes = [vp, vp, vp, vp, i64, vp, i64, kpp, vp, vp, vp, sz, vp]
     lib.dwg_gwn_grad.argtypes = [vp, vp, vp, vp, i64, vp, i64, kpp, vp, vp, vp, vp, sz, vp]
+    lib.dwg_gwn_grad_static.argtypes = [vp, vp, vp, vp, i64, vp, i64, kpp, vp, vp, vp, vp]
     lib.dwg_iterate.argtypes = [vp, vp, vp, i64, vp, kpp, ctypes.POINTER(IterateParams),
                                 ctypes.POINTER(IterStat), ctypes.POINTER(ctypes.c_int), vp, sz, vp]
     lib.dwg_init_normals.argtypes = [i32, ctypes.c_uint64, vp, i64, vp, vp, vp, sz, vp]
@@ -93,7 +94,7 @@ def load():
     lib.dwg_features.argtypes = [vp, i64, i64, vp, vp, sz, vp]
     lib.dwg_mlp_infer.argtypes = [vp, vp, i64, vp, vp, sz, vp]
     lib.dwg_mlp_train_step.argtypes = [vp, vp, vp, i64, f32, vp, vp, vp, i64, vp, vp, vp, sz, vp]
-    for name in ["dwg_gwn_eval", "dwg_gwn_grad", "dwg_iterate", "dwg_init_normals", "dwg_knn",
+    for name in ["dwg_gwn_eval", "dwg_gwn_grad", "dwg_gwn_grad_static", "dwg_iterate", "dwg_init_normals", "dwg_knn",
                  "dwg_delta_knn_mean", "dwg_delta_anchor_mean", "dwg_features", "dwg_mlp_infer",
                  "dwg_mlp_train_step", "dwg_octree", "dwg_delta_knn_window", "dwg_voronoi_area", "dwg_mc_cells",
                  "dwg_iterate_mc", "dwg_level_set"]:
@@ -103,7 +104,7 @@ def load():
 
 
 EXPORTED = ["dwg_version", "dwg_status_string", "dwg_last_error", "dwg_workspace_bytes", "dwg_gwn_eval",
-            "dwg_gwn_grad", "dwg_iterate", "dwg_init_normals", "dwg_knn", "dwg_delta_knn_mean",
+            "dwg_gwn_grad", "dwg_gwn_grad_static", "dwg_iterate", "dwg_init_normals", "dwg_knn", "dwg_delta_knn_mean",
             "dwg_delta_anchor_mean", "dwg_mlp_param_count", "dwg_mlp_blob_bytes", "dwg_features", "dwg_mlp_infer",
             "dwg_mlp_train_step", "dwg_octree", "dwg_delta_knn_window", "dwg_voronoi_area", "dwg_mc_workspace_bytes",
             "dwg_mc_cells", "dwg_iterate_mc", "dwg_level_set"]
@@ -209,6 +210,29 @@ def gwn(P, N, area, delta, Q, params: Params | None = None, grad=True, ws=None, 
     _check(_run(dev, lib.dwg_gwn_eval, _ptr(P), _ptr(N), _ptr(area), _ptr(delta), n, _ptr(Q), m, ctypes.byref(kp),
         _ptr(w), _ptr(wm), _ptr(ws), ws.numel(), _stream(dev)))
     return (w, wm) if want_wmean else w
+
+
+def gwn_static(P, N, area, delta, Q, params: Params | None = None, want_wmean=False):
+    """w [m] and grad w [3, m] through dwg_gwn_grad_static (no workspace: the library's
+    static scratch; sizes whose scratch exceeds it raise)."""
+    lib = load()
+    params = params or Params()
+    P = _pts(P, "P")
+    n = P.shape[1]
+    dev = P.device
+    _dev(N, "N", shape=(3, n), device=dev)
+    _dev(area, "area", shape=(n,), device=dev)
+    if delta is not None:
+        _dev(delta, "delta", shape=(n,), device=dev)
+    Q = _pts(Q, "Q", device=dev)
+    m = Q.shape[1]
+    w = torch.empty(m, dtype=torch.float32, device=dev)
+    g = torch.empty((3, m), dtype=torch.float32, device=dev)
+    wm = torch.empty(1, dtype=torch.float64, device=dev) if want_wmean else None
+    kp = params.c()
+    _check(_run(dev, lib.dwg_gwn_grad_static, _ptr(P), _ptr(N), _ptr(area), _ptr(delta), n, _ptr(Q), m,
+                ctypes.byref(kp), _ptr(w), _ptr(g), _ptr(wm), _stream(dev)))
+    return (w, g, wm) if want_wmean else (w, g)
 
 
 def iterate(P, area, delta, N, params: Params | None = None, max_iters=50, fixed_iters=False, eps_deg=0.1,

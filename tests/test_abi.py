@@ -144,6 +144,20 @@ def test_octree_area_and_level_set_validation():
     assert ntri.value == 0
 
 
+def test_static_scratch_entry_validates_before_the_device():
+    """dwg_gwn_grad_static rejects NULLs and sizes whose scratch exceeds its static array
+    before any HIP call (so on a machine without a GPU too)."""
+    lib = dwg.load()
+    kp = dwg.Params(lam=10.0).c()
+    assert lib.dwg_gwn_grad_static(None, FAKE, FAKE, None, 10, FAKE, 10, ctypes.byref(kp), None, FAKE, None,
+                                   None) == dwg.DWG_E_INVALID
+    assert lib.dwg_gwn_grad_static(FAKE, FAKE, FAKE, None, 10, FAKE, 10, ctypes.byref(kp), None, None, None,
+                                   None) == dwg.DWG_E_INVALID
+    assert lib.dwg_gwn_grad_static(FAKE, FAKE, FAKE, None, 700_000, FAKE, 700_000, ctypes.byref(kp), None, FAKE,
+                                   None, None) == dwg.DWG_E_INVALID
+    assert "static scratch" in lib.dwg_last_error().decode()
+
+
 def test_single_hip_runtime_in_process():
     """libdwg must bind to the HIP runtime torch already loaded (one libamdhip64 mapped)."""
     dwg.load()
