@@ -271,9 +271,11 @@ def octree(P, leaf=32):
         cap = int(cnt)
 
 
-def tree_gwn(P, N, area, delta, Q, lam=0.0, eps=0.0, beta=2.3, leaf=32, grad=True, visits=False):
-    """Octree-approximated w [m], grad w [3,m] (or None), flags [m] (and visited-node counts
-    [m] when visits=True): Sec. 5.2 traversal with opening radius max(beta r, r + dmax)."""
+def tree_gwn(P, N, area, delta, Q, lam=0.0, eps=0.0, beta=2.3, leaf=32, grad=True, work=False):
+    """Octree-approximated w [m], grad w [3,m] (or None), flags [m] (and, when work=True, per
+    query [m, 4] = visited nodes, far nodes taken as one dipole, source pairs summed at
+    leaves, sources inside the far nodes): Sec. 5.2 traversal with opening radius
+    max(beta r, r + dmax)."""
     lib = _load()
     P = _d(P)
     n = P.shape[1]
@@ -285,12 +287,12 @@ def tree_gwn(P, N, area, delta, Q, lam=0.0, eps=0.0, beta=2.3, leaf=32, grad=Tru
     w = np.zeros(m)
     g = np.zeros((3, m)) if grad else None
     fl = np.zeros(m, dtype=np.int32)
-    vis = np.zeros(m, dtype=np.int64)
+    wk = np.zeros((m, 4), dtype=np.int64)
     rc = lib.orc_tree_gwn(_p(P), _p(N), _p(area), _p(delta), n, _p(Q), m, float(lam), float(eps), float(beta),
-                          int(leaf), _p(w), _p(g), _p(fl, ctypes.c_int32), _p(vis, ctypes.c_int64))
+                          int(leaf), _p(w), _p(g), _p(fl, ctypes.c_int32), _p(wk, ctypes.c_int64))
     if rc != 0:
         raise ValueError("orc_tree_gwn rejected its arguments")
-    return (w, g, fl, vis) if visits else (w, g, fl)
+    return (w, g, fl, wk) if work else (w, g, fl)
 
 
 def voronoi_area(P, m=15):

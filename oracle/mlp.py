@@ -35,6 +35,66 @@ def bf16(x):
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+U32 = 2.0 ** -24  # unit roundoff of float32
+
+
+def _bf16_tie_gap(v):
+    """Distance of each value to the nearest bfloat16 rounding boundary (the midpoint of two
+    consecutive bfloat16 numbers, exactly representable in float32)."""
+    v = np.asarray(v, np.float64)
+    u = np.ascontiguousarray(v.astype(np.float32)).view(np.uint32)
+    lo = (u & np.uint32(0xFFFF0000)) | np.uint32(0x8000)
+    hi_prev = ((u & np.uint32(0xFFFF0000)) - np.uint32(0x10000)) | np.uint32(0x8000)
+    m1 = lo.view(np.float32).astype(np.float64)
+    m0 = hi_prev.view(np.float32).astype(np.float64)
+    return np.minimum(np.abs(v - m1), np.abs(v - m0))
+
+
+def _bf16_ulp(v):
+    """Spacing of the bfloat16 numbers around each value (2^(e - 7) for |v| in [2^e, 2^(e+1)))."""
+    v = np.abs(np.asarray(v, np.float64))
+    e = np.floor(np.log2(np.maximum(v, 2.0 ** -126)))
+    return 2.0 ** (e - 7)
+
+
+def forward_bound(blob, X, x_rel_err=0.0):
+    """A bound, per row, on |y_gpu - y| between this oracle's forward pass and any float32
+    evaluation of the same network on BF16-rounded operands (bound [B]), with y [B, 3].
+
+    Interval propagation, layer by layer: a float32 dot product of K terms is off by at most
+    K u sum|terms| (u = 2^-24); an activation whose uncertainty reaches a bfloat16 rounding
+    boundary may round to the neighbouring bfloat16 value (one more ulp); ReLU and the
+    rounding to nearest are 1-Lipschitz otherwise. With x_rel_err > 0 the inputs carry that
+    relative error (features computed in float32) and may round either way too."""
+    p = unpack(blob)
+    X = np.asarray(X, np.float64)
+    W1, W2, W3 = bf16(p["W1"]), bf16(p["W2"]), bf16(p["W3"])
+    X0 = bf16(X)
+    dX = np.zeros_like(X0)
+    if x_rel_err > 0:
+        ex = x_rel_err * np.abs(X)
+        dX = ex + np.where(_bf16_tie_gap(X) <= ex, _bf16_ulp(X), 0.0)
+
+    def layer(h, dh, W, b, K):
+        z = h @ W.T + b
+        dz = np.abs(dh) @ np.abs(W).T + 2 * K * U32 * (np.abs(h) @ np.abs(W).T + np.abs(b))
+        return z, dz
+
+    def act(z, dz):
+        a = np.maximum(z, 0.0)
+        hr = bf16(a)
+        # the float32 side's activation lies within dz of a; its rounding within one ulp
+        flip = _bf16_tie_gap(a) <= dz
+        return hr, dz + np.where(flip, _bf16_ulp(a), 0.0)
+
+    z1, dz1 = layer(X0, dX, W1, p["b1"], IN)
+    h1, dh1 = act(z1, dz1)
+    z2, dz2 = layer(h1, dh1, W2, p["b2"], HID)
+    h2, dh2 = act(z2, dz2)
+    y, dy = layer(h2, dh2, W3, p["b3"], HID)
+    return y, np.linalg.norm(dy, axis=1)
+
+
 def unpack(blob):
     """Parameter blob (W1, b1, W2, b2, W3, b3 row-major) -> dict of float64 arrays."""
     blob = np.asarray(blob, np.float64)

@@ -228,9 +228,11 @@ typedef struct {
   int want_grad;
 } tctx;
 
-static void visit(const tctx* c, int64_t k, const double q[3], acc4* acc, int32_t* flag, int64_t* visits) {
+/* work[0] counts the visited nodes, work[1] the far nodes taken as one dipole, work[2] the
+ * source pairs summed at leaves, work[3] the sources inside the far nodes. */
+static void visit(const tctx* c, int64_t k, const double q[3], acc4* acc, int32_t* flag, int64_t work[4]) {
   const tnode* nd = &c->nodes[k];
-  ++*visits;
+  ++work[0];
   const double dx = nd->cm[0] - q[0], dy = nd->cm[1] - q[1], dz = nd->cm[2] - q[2];
   const double dist = sqrt(dx * dx + dy * dy + dz * dz);
   double crit = c->beta * nd->r;
@@ -238,10 +240,13 @@ static void visit(const tctx* c, int64_t k, const double q[3], acc4* acc, int32_
   if (crit > 0.0 && fabs(dist - crit) <= 1e-7 * crit) *flag = 1;
   if (dist > crit) {
     dipole(acc, dx, dy, dz, nd->M, 0.0, c->s, c->want_grad);
+    ++work[1];
+    work[3] += nd->end - nd->start;
     return;
   }
   if (nd->leaf) {
     const int64_t n = c->n;
+    work[2] += nd->end - nd->start;
     for (int64_t t = nd->start; t < nd->end; ++t) {
       const int64_t j = c->perm[t];
       double fl = c->D ? c->D[j] : 0.0;
@@ -254,14 +259,15 @@ static void visit(const tctx* c, int64_t k, const double q[3], acc4* acc, int32_
     }
     return;
   }
-  for (int i = 0; i < nd->nchild; ++i) visit(c, nd->child[i], q, acc, flag, visits);
+  for (int i = 0; i < nd->nchild; ++i) visit(c, nd->child[i], q, acc, flag, work);
 }
 
-/* Octree-approximated w, grad w (may be NULL), flags and per-query visited-node counts
- * (may be NULL) at m queries. Arguments as orc_gwn plus beta (> 0) and leaf (>= 1). */
+/* Octree-approximated w, grad w (may be NULL), flags and per-query work [m][4] (visited
+ * nodes, far dipoles, leaf pairs, sources inside the far nodes; may be NULL) at m queries. Arguments as orc_gwn plus beta
+ * (> 0) and leaf (>= 1). */
 int orc_tree_gwn(const double* P, const double* Nrm, const double* A, const double* D, int64_t n,
                  const double* Q, int64_t m, double lambda, double eps, double beta, int leaf, double* w,
-                 double* g, int32_t* flag, int64_t* visits) {
+                 double* g, int32_t* flag, int64_t* work) {
   if (!P || !Nrm || !A || !Q || !w || n < 1 || m < 0 || !(lambda >= 0.0) || !(eps >= 0.0) || !(beta > 0.0) ||
       leaf < 1)
     return -1;
@@ -309,13 +315,14 @@ int orc_tree_gwn(const double* P, const double* Nrm, const double* A, const doub
     acc4 acc;
     memset(&acc, 0, sizeof acc);
     int32_t fl = 0;
-    int64_t vis = 0;
-    visit(&c, 0, q, &acc, &fl, &vis);
+    int64_t wk[4] = {0, 0, 0, 0};
+    visit(&c, 0, q, &acc, &fl, wk);
     w[i] = nval(&acc.w);
     if (g)
       for (int d = 0; d < 3; ++d) g[d * m + i] = nval(&acc.g[d]);
     if (flag) flag[i] = fl;
-    if (visits) visits[i] = vis;
+    if (work)
+      for (int d = 0; d < 4; ++d) work[4 * i + d] = wk[d];
   }
   free(nodes);
   free(perm);

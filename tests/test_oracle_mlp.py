@@ -115,3 +115,31 @@ def test_feature_invariants():
     # an anchor never sees itself
     stride = 6000 // 512
     assert np.all(norms[::stride, 0] > 0)
+
+
+def test_forward_bound_covers_a_float32_evaluation():
+    """om.forward_bound bounds |y_fp32 - y| for any float32 evaluation on BF16 operands: a
+    float32 NumPy forward pass (its own summation order, its own BF16 flips of activations
+    near a rounding boundary) stays inside the bound on every row, including rows with such
+    flips, and the bound is not vacuous (median relative bound well below 1)."""
+    from oracle import mlp as om
+    from paper_2405_13839_amd import mlp_init
+    blob = mlp_init.init_params(3)
+    rng = np.random.default_rng(4)
+    blob[om.N_PARAMS - 3 - 3 * 128 - 128:] += rng.standard_normal(3 + 3 * 128 + 128).astype(np.float32) * 0.05
+    X = rng.standard_normal((4000, 48)).astype(np.float32)
+    p = om.unpack(blob)
+
+    def r32(a):
+        return om.bf16(a).astype(np.float32)
+
+    h1 = r32(np.maximum(r32(X) @ r32(p["W1"]).T + p["b1"].astype(np.float32), 0))
+    h2 = r32(np.maximum(h1 @ r32(p["W2"]).T + p["b2"].astype(np.float32), 0))
+    y32 = (h2 @ r32(p["W3"]).T + p["b3"].astype(np.float32)).astype(np.float64)
+    y, bound = om.forward_bound(blob, X)
+    err = np.linalg.norm(y32 - y, axis=1)
+    assert np.all(err <= bound)
+    assert np.median(bound / np.linalg.norm(y, axis=1)) < 0.05
+    # some rows do differ by a flip (the bound is exercised, not only the accumulation term)
+    y_noflip, _, _ = om.forward(blob, X)
+    assert np.any(err > 1e-4 * np.linalg.norm(y_noflip, axis=1))

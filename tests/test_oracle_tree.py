@@ -138,3 +138,21 @@ def test_far_test_keeps_the_clamp():
         wt, gt, _ = oracle.tree_gwn(P, N, a, d, q, lam=lam, beta=2.3, leaf=1)
         np.testing.assert_allclose(wt, w, rtol=1e-14)
         np.testing.assert_allclose(gt, g, rtol=1e-14, atol=1e-300)
+
+
+def test_traversal_work_partitions_the_sources():
+    """Per query, the far nodes and the leaf pairs of the traversal cover every source exactly
+    once (a far node stands for its sources), for any opening factor; a query far from the
+    cloud takes the root as one dipole; with beta -> infinity only nodes of zero radius (one
+    point, or coincident points) can still be far, so far nodes hold one point each here."""
+    c = synth.torus_ellipsoids(6000, seed=9)
+    d = oracle.anchor_delta(c.P)
+    Q = np.concatenate([c.P[:, ::37], np.array([[50.0], [0.0], [0.0]], np.float32)], axis=1)
+    _, _, _, wk = oracle.tree_gwn(c.P, c.N_true, c.area, d, Q, lam=10.0, beta=2.3, leaf=16, grad=False,
+                                  work=True)
+    np.testing.assert_array_equal(wk[:, 2] + wk[:, 3], c.n)
+    assert wk[:-1, 1].min() > 0 and wk[:-1, 2].min() > 0
+    assert tuple(wk[-1, 1:]) == (1, 0, c.n)
+    _, _, _, wk = oracle.tree_gwn(c.P, c.N_true, c.area, d, Q[:, :20], beta=1e9, leaf=16, grad=False, work=True)
+    np.testing.assert_array_equal(wk[:, 2] + wk[:, 3], c.n)
+    np.testing.assert_array_equal(wk[:, 1], wk[:, 3])
