@@ -160,6 +160,19 @@ dwg_status dwg_gwn_grad_static(const float* P, const float* N, const float* area
 dwg_status dwg_octree(const float* P, int64_t n, int leaf, int32_t* perm, int32_t* nodes, int64_t cap,
                       int64_t* count, void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * dwg_octree_work -- the work of the octree mode's traversal (Sec. 5.2) for m queries Q:
+ * *far (HOST) = the number of (query, node) pairs the traversal takes as one dipole,
+ * *pairs (HOST) = the number of (query, source) pairs it sums one by one at leaves, both
+ * totalled over the queries. They depend on the positions, areas, radii and kp (the opening
+ * decisions), not on the normals. Synchronous. Requires kp->tree_beta > 0 and n < 2^30.
+ * Workspace: dwg_workspace_bytes(n, m, kp). Errors as dwg_gwn_eval (*far and *pairs are set
+ * to 0 first).
+ */
+dwg_status dwg_octree_work(const float* P, const float* area, const float* delta, int64_t n, const float* Q,
+                           int64_t m, const dwg_kernel_params* kp, int64_t* far, int64_t* pairs, void* ws,
+                           size_t ws_bytes, void* stream);
+
 /* Grid of the level-set update (Sec. 4.3, Algorithm 1). */
 typedef struct dwg_mc_params {
   int depth;    /* cells per axis = 2^depth over the octree frame, 1..16 (paper: 8-13) */

@@ -334,6 +334,46 @@ dwg_status dwg_gwn_grad_static(const float* P, const float* N, const float* area
   return gwn_common(P, N, area, delta, n, Q, m, &kp, true, w, grad, wmean, ws, kStaticScratchBytes, stream);
 }
 
+dwg_status dwg_octree_work(const float* P, const float* area, const float* delta, int64_t n, const float* Q,
+                           int64_t m, const dwg_kernel_params* kpp, int64_t* far, int64_t* pairs, void* ws,
+                           size_t ws_bytes, void* stream) {
+  if (far) *far = 0;
+  if (pairs) *pairs = 0;
+  DWG_CHECK(P && area && Q && far && pairs, "P, area, Q, far and pairs must not be NULL");
+  DWG_CHECK(n >= 1 && m >= 1, "n and m must be >= 1 (got n=%lld, m=%lld)", (long long)n, (long long)m);
+  DWG_CHECK(n < (int64_t(1) << 30) && m < (int64_t(1) << 31), "need n < 2^30 and m < 2^31");
+  DWG_PROPAGATE(check_kp(kpp));
+  DWG_CHECK(kpp && tree_mode(*kpp), "kp->tree_beta must be > 0 (octree mode)");
+  const dwg_kernel_params kp = *kpp;
+  Carver need(nullptr);
+  carve_gwn(need, n, m, 1, false, nullptr);
+  carve_tree(need, n, tree_leaf(kp), kp.tree_beta, nullptr);
+  need.take<unsigned long long>(2);
+  DWG_CHECK(ws || ws_bytes == 0, "ws is NULL but ws_bytes > 0");
+  if (!ws || ws_bytes < need.used) {
+    set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, need.used);
+    return DWG_E_WORKSPACE;
+  }
+  DWG_PROPAGATE(check_device());
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool same = (Q == P && m == n);
+  Carver c(ws);
+  GwnWork wk;
+  TreeWork tw;
+  carve_gwn(c, n, m, 1, same, &wk);
+  carve_tree(c, n, tree_leaf(kp), kp.tree_beta, &tw);
+  unsigned long long* cnt = c.take<unsigned long long>(2);
+  DWG_PROPAGATE(tree_build(P, area, delta, n, kp.eps, tw, wk.perm_s, st));
+  if (!same) DWG_PROPAGATE(spatial_sort(Q, m, nullptr, 0.0f, wk.sort, wk.perm_q, st));
+  DWG_PROPAGATE(tree_work(Q, m, wk.perm_q, tw, cnt, st));
+  unsigned long long h[2] = {0, 0};
+  DWG_TRY_HIP(hipMemcpyAsync(h, cnt, sizeof h, hipMemcpyDeviceToHost, st));
+  DWG_TRY_HIP(hipStreamSynchronize(st));
+  *far = (int64_t)h[0];
+  *pairs = (int64_t)h[1];
+  return DWG_OK;
+}
+
 dwg_status dwg_iterate(const float* P, const float* area, const float* delta, int64_t n,
                        float* N_inout, const dwg_kernel_params* kpp, const dwg_iterate_params* ip,
                        dwg_iter_stat* stats_host, int* iters_done, void* ws, size_t ws_bytes,

@@ -186,6 +186,10 @@ dwg_status tree_moments(const GwnWork& w, const TreeWork& t, hipStream_t st);
 // Octree-approximated w (and grad) at the sorted queries of w into w.part (split 1).
 dwg_status tree_eval(const float* Q, int64_t m, const dwg_kernel_params& kp, bool grad, const GwnWork& w,
                      const TreeWork& t, hipStream_t st);
+// Totals over the m sorted queries of the traversal's far dipoles (out[0]) and leaf pairs
+// (out[1]); out is 2 device counters.
+dwg_status tree_work(const float* Q, int64_t m, const int32_t* qperm, const TreeWork& t, unsigned long long* out,
+                     hipStream_t st);
 dwg_status tree_export(const TreeWork& t, int32_t* nodes_out, int64_t cap_out, int64_t* count_host,
                        hipStream_t st);
 // Stable LSD radix sort of (key, value) pairs on the low `bits` bits, 8 bits per pass,

@@ -594,6 +594,75 @@ __global__ __launch_bounds__(256) void k_tree_eval(const float* __restrict__ Q, 
   for (int a = 0; a < NA; ++a) part[a * mpad + qi] = KAHAN ? sum[a] - cmp[a] : sum[a];
 }
 
+// Work of the traversal, totalled over the queries: far nodes taken as one dipole and source
+// pairs summed at leaves. The decisions are those of k_tree_eval (the same FP64 opening test,
+// the same wave-wide walk), without its arithmetic; lanes past m do not count. Integer atomics
+// make the totals independent of the order of the blocks.
+__global__ __launch_bounds__(256) void k_tree_work(const float* __restrict__ Q, int64_t m,
+                                                   const int32_t* __restrict__ qperm, const int4* __restrict__ node,
+                                                   const double4* __restrict__ geo,
+                                                   const int32_t* __restrict__ total_p, int64_t cap, int64_t n_src,
+                                                   unsigned long long* __restrict__ out) {
+  __shared__ unsigned long long red[2][4];
+  const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = qi < m;
+  const int64_t o = qperm[live ? qi : m - 1];
+  const double dqx = Q[o], dqy = Q[m + o], dqz = Q[2 * m + o];
+  int nn = __builtin_amdgcn_readfirstlane(*total_p);
+  if (nn > cap) nn = (int)cap;
+  unsigned long long nfar = 0, npair = 0;
+  int skip_to = 0;
+  int i = 0;
+  while (i < nn) {
+    const int4 nd = node[i];
+    const double4 g = geo[i];
+    const int nskip = __builtin_amdgcn_readfirstlane(nd.z);
+    bool open = false, direct = false;
+    if (i >= skip_to) {
+      const double dx = g.x - dqx, dy = g.y - dqy, dz = g.z - dqz;
+      const double d2 = dx * dx + dy * dy + dz * dz;
+      if (d2 > g.w) {
+        ++nfar;
+        skip_to = nskip;
+      } else if (nd.w >> 8) {
+        direct = true;
+      } else {
+        open = true;
+      }
+    }
+    int next;
+    if (__any(open)) {
+      next = i + 1;
+    } else {
+      if (direct) {
+        const int s1 = nd.y < n_src ? nd.y : (int)n_src;
+        npair += (unsigned long long)(s1 - nd.x);
+      }
+      next = nskip > i ? nskip : i + 1;
+    }
+    i = __builtin_amdgcn_readfirstlane(next);
+  }
+  if (!live) nfar = npair = 0;
+  for (int off = 32; off > 0; off >>= 1) {
+    nfar += __shfl_xor(nfar, off, 64);
+    npair += __shfl_xor(npair, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wv] = nfar;
+    red[1][wv] = npair;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(&out[0], red[0][0] + red[0][1] + red[0][2] + red[0][3]);
+    atomicAdd(&out[1], red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+  }
+}
+
+__global__ void k_zero_u64x2(unsigned long long* __restrict__ a) {
+  if (threadIdx.x < 2) a[threadIdx.x] = 0ull;
+}
+
 __global__ void k_copy_i32(const int32_t* __restrict__ a, int64_t n, int32_t* __restrict__ b) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     b[i] = a[i];
@@ -775,6 +844,16 @@ dwg_status tree_eval(const float* Q, int64_t m, const dwg_kernel_params& kp, boo
   DWG_TREE_CASE(false, true, true)
   DWG_TREE_CASE(false, true, false)
 #undef DWG_TREE_CASE
+  DWG_TRY_LAUNCH();
+  return DWG_OK;
+}
+
+dwg_status tree_work(const float* Q, int64_t m, const int32_t* qperm, const TreeWork& t, unsigned long long* out,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_u64x2, dim3(1), dim3(64), 0, st, out);
+  DWG_TRY_LAUNCH();
+  hipLaunchKernelGGL(k_tree_work, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, st, Q, m, qperm, t.node, t.geo,
+                     t.off + t.n, t.cap, t.n, out);
   DWG_TRY_LAUNCH();
   return DWG_OK;
 }

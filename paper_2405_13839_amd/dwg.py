@@ -72,6 +72,8 @@ def load():
     lib.dwg_gwn_eval.argtypes = [vp, vp, vp, vp, i64, vp, i64, kpp, vp, vp, vp, sz, vp]
     lib.dwg_gwn_grad.argtypes = [vp, vp, vp, vp, i64, vp, i64, kpp, vp, vp, vp, vp, sz, vp]
     lib.dwg_gwn_grad_static.argtypes = [vp, vp, vp, vp, i64, vp, i64, kpp, vp, vp, vp, vp]
+    lib.dwg_octree_work.argtypes = [vp, vp, vp, i64, vp, i64, kpp, ctypes.POINTER(i64), ctypes.POINTER(i64), vp,
+                                    sz, vp]
     lib.dwg_iterate.argtypes = [vp, vp, vp, i64, vp, kpp, ctypes.POINTER(IterateParams),
                                 ctypes.POINTER(IterStat), ctypes.POINTER(ctypes.c_int), vp, sz, vp]
     lib.dwg_init_normals.argtypes = [i32, ctypes.c_uint64, vp, i64, vp, vp, vp, sz, vp]
@@ -96,8 +98,8 @@ def load():
     lib.dwg_mlp_train_step.argtypes = [vp, vp, vp, i64, f32, vp, vp, vp, i64, vp, vp, vp, sz, vp]
     for name in ["dwg_gwn_eval", "dwg_gwn_grad", "dwg_gwn_grad_static", "dwg_iterate", "dwg_init_normals", "dwg_knn",
                  "dwg_delta_knn_mean", "dwg_delta_anchor_mean", "dwg_features", "dwg_mlp_infer",
-                 "dwg_mlp_train_step", "dwg_octree", "dwg_delta_knn_window", "dwg_voronoi_area", "dwg_mc_cells",
-                 "dwg_iterate_mc", "dwg_level_set"]:
+                 "dwg_mlp_train_step", "dwg_octree", "dwg_octree_work", "dwg_delta_knn_window", "dwg_voronoi_area",
+                 "dwg_mc_cells", "dwg_iterate_mc", "dwg_level_set"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -106,8 +108,8 @@ def load():
 EXPORTED = ["dwg_version", "dwg_status_string", "dwg_last_error", "dwg_workspace_bytes", "dwg_gwn_eval",
             "dwg_gwn_grad", "dwg_gwn_grad_static", "dwg_iterate", "dwg_init_normals", "dwg_knn", "dwg_delta_knn_mean",
             "dwg_delta_anchor_mean", "dwg_mlp_param_count", "dwg_mlp_blob_bytes", "dwg_features", "dwg_mlp_infer",
-            "dwg_mlp_train_step", "dwg_octree", "dwg_delta_knn_window", "dwg_voronoi_area", "dwg_mc_workspace_bytes",
-            "dwg_mc_cells", "dwg_iterate_mc", "dwg_level_set"]
+            "dwg_mlp_train_step", "dwg_octree", "dwg_octree_work", "dwg_delta_knn_window", "dwg_voronoi_area",
+            "dwg_mc_workspace_bytes", "dwg_mc_cells", "dwg_iterate_mc", "dwg_level_set"]
 
 
 def version() -> str:
@@ -401,6 +403,26 @@ def octree(P, leaf: int = 0, ws=None):
     _check(_run(P.device, lib.dwg_octree, _ptr(P), n, int(leaf), _ptr(perm), _ptr(nodes), cap, ctypes.byref(cnt),
         _ptr(ws), ws.numel(), _stream(P.device)))
     return perm, nodes[:cnt.value]
+
+
+def octree_work(P, area, delta, Q, params: Params, ws=None):
+    """(far dipoles, leaf pairs) of the octree traversal for the queries Q, totalled."""
+    lib = load()
+    P = _pts(P, "P")
+    n = P.shape[1]
+    _dev(area, "area", shape=(n,), device=P.device)
+    if delta is not None:
+        _dev(delta, "delta", shape=(n,), device=P.device)
+    Q = _pts(Q, "Q", device=P.device)
+    m = Q.shape[1]
+    if ws is None:
+        ws = workspace(n, m, P.device, params)
+    _dev(ws, "ws", dtype=torch.uint8, device=P.device)
+    kp = params.c()
+    far, pairs = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(_run(P.device, lib.dwg_octree_work, _ptr(P), _ptr(area), _ptr(delta), n, _ptr(Q), m, ctypes.byref(kp),
+                ctypes.byref(far), ctypes.byref(pairs), _ptr(ws), ws.numel(), _stream(P.device)))
+    return far.value, pairs.value
 
 
 def pca_normals(P, ws=None) -> torch.Tensor:

@@ -2,7 +2,7 @@
 sphere (2K, plain), torus + 2 ellipsoids (100K and 1M, screened), superquadrics + thin
 plates (5M, plain and screened) and 20 ellipsoids / tori (15M, screened). All sources take
 part; a seeded sample of queries is evaluated on the GPU and recomputed one by one by the
-FP64 oracle; the 1M and 5M configurations are also run as full launches (every point a
+FP64 oracle; the 1M, 5M and 15M configurations are also run as full launches (every point a
 query) and compared on a seeded 10K-point subset. Inputs (points, random unit normals,
 anchor radius by scipy's cKDTree) come from the seeded generators, never from the GPU path.
 Prints e_w / e_g per configuration."""
@@ -58,27 +58,43 @@ FULL_LAUNCH = [
     ("C3 torus+ellipsoids 1M screened", lambda: synth.torus_ellipsoids(1_000_000, seed=102), 10.0),
     ("C4 superquadrics+plates 5M", lambda: synth.superquadrics_plates(5_000_000, seed=103), 0.0),
     ("C4 superquadrics+plates 5M screened", lambda: synth.superquadrics_plates(5_000_000, seed=103), 10.0),
+    ("C5 ellipsoids+tori 15M screened", lambda: synth.ellipsoids_tori(15_000_000, seed=104), 10.0),
 ]
 
 
 @pytest.mark.parametrize("name,gen,lam", FULL_LAUNCH, ids=[c[0] for c in FULL_LAUNCH])
-def test_full_launch_10k_subset(name, gen, lam):
+def test_full_launch_10k_subset(name, gen, lam, capsys):
     """A configuration evaluated as the iteration does: every point is a query of one launch
     (all query blocks, the library's default split), and w and grad w of a seeded 10K-point
     subset are compared with the FP64 oracle. In the 5M scene, scaling absolute positions by
     kappa in FP32 would flip the clamp branch of a few near pairs (e_g ~ 6e-2 at one query in
-    10K); the kernels take kappa (p - q) from differences."""
+    10K); the kernels take kappa (p - q) from differences. The 15M launch takes about two
+    minutes on the GPU and the oracle's subset about as long on 16 cores, so each stage
+    reports when it is done."""
     from paper_2405_13839_amd import dwg
+
+    def done(msg):
+        with capsys.disabled():
+            print(f"\n[full launch] {name}: {msg}", flush=True)
+
     c = gen()
     rng = np.random.default_rng(17)
     N = unit_rows(rng, c.n)
     d = anchor_radius(c.P)
     sel = np.sort(rng.choice(c.n, 10_000, replace=False))
+    done(f"inputs ready (n={c.n})")
     Pc = cuda(c.P)
     w, g = dwg.gwn(Pc, cuda(N), cuda(c.area), cuda(d), Pc, dwg.Params(lam=lam))
     wg, gg = host(w)[sel], host(g)[:, sel]
     del w, g, Pc
-    w_ref, g_ref, flag = oracle.gwn(c.P, N, c.area, d, np.ascontiguousarray(c.P[:, sel]), lam=lam)
+    done("GPU launch done")
+    parts = []
+    for k, part in enumerate(np.array_split(sel, 4)):
+        parts.append(oracle.gwn(c.P, N, c.area, d, np.ascontiguousarray(c.P[:, part]), lam=lam))
+        done(f"oracle part {k + 1}/4 done")
+    w_ref = np.concatenate([p[0] for p in parts])
+    g_ref = np.concatenate([p[1] for p in parts], axis=1)
+    flag = np.concatenate([p[2] for p in parts])
     ew, eg = e_w(wg, w_ref), e_g(gg, g_ref, skip=flag)
     print(f"[accuracy] {name} full launch: 10K-point subset e_w={ew:.2e} e_g={eg:.2e} "
           f"flagged={int(flag.sum())}")

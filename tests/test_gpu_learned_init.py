@@ -37,15 +37,24 @@ def test_init_normals_mlp_matches_oracle():
     ok = ~amb
     cos = np.sum(N.T[ok] * yhat[ok], axis=1)
     ang = np.degrees(np.arccos(np.clip(cos, -1, 1)))
-    assert np.mean(ang < 1.0) > 0.99, np.percentile(ang, [50, 99, 99.9])
+    # features computed in float32 carry ~1e-6 relative error (measured <= 3.6e-7 absolute)
+    y, ybound = om.forward_bound(blob, f[ok], x_rel_err=2e-6)
+    bound = np.degrees(np.arcsin(np.minimum(1.0, ybound / np.linalg.norm(y, axis=1))))
+    print(f"[mlp init] flagged {amb.mean():.4f} angle p50 {np.median(ang):.2e} p99 {np.percentile(ang, 99):.2e} "
+          f"p99.9 {np.percentile(ang, 99.9):.2e} max {ang.max():.2e}; bound p50 {np.median(bound):.2e}")
+    # every row whose neighbour order is unambiguous is within the rigorous float32/BF16 bound,
+    # and 99.9% of them within 0.05 deg
+    assert np.all(ang <= bound + 1e-6)
+    assert np.percentile(ang, 99.9) <= 0.05 and amb.mean() < 0.01
     np.testing.assert_allclose(np.linalg.norm(N.astype(np.float64), axis=0), 1.0, atol=1e-5)
 
 
 @pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights missing")
 def test_learned_init_gain_over_random():
-    """Held-out shapes (seeds 20000+) at 50K points, screened lambda = 10, anchor radius: from the learned
-    init the iteration passes its convergence test with <= 6 deg mean angle error and > 99%
-    orientation agreement; from random normals it does not reach either within 100
+    """Held-out shapes (seeds 20000+) at 50K points, screened lambda = 10, anchor radius: from the
+    learned init the iteration passes its convergence test on every shape with > 99%
+    orientation agreement, at <= 5 deg mean angle error on average and on at least three of
+    the four (the fourth measured 5.6 deg); from random normals it reaches neither within 100
     iterations on most shapes."""
     dwg = _dwg()
     mlp = mlp_init.load_params(WEIGHTS, "cuda")
@@ -61,8 +70,11 @@ def test_learned_init_gain_over_random():
             rep = metrics.orientation_report(host(N), c.N_true, c.comp)
             row[kind] = (st == dwg.DWG_OK, stats.shape[0], rep["mae_deg"], rep["agree"])
         res.append(row)
+        print("[gain]", seed, row)
     for row in res:
         conv, iters, mae, agree = row["mlp"]
         assert conv and iters < 100 and mae <= 6.0 and agree > 0.99, row
+    maes = [r["mlp"][2] for r in res]
+    assert np.mean(maes) <= 5.0 and sum(m <= 5.0 for m in maes) >= 3, maes
     assert sum(1 for row in res if row["random"][2] > 10.0) >= 3, res
     assert np.mean([r["mlp"][1] for r in res]) < np.mean([r["random"][1] for r in res])

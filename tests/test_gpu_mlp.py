@@ -22,7 +22,7 @@ def _rel_fro(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
 
 
-@pytest.mark.parametrize("n,n_anchor", [(20_000, 4096), (6000, 512), (100, 17)])
+@pytest.mark.parametrize("n,n_anchor", [(20_000, 4096), (6000, 512), (100, 17), (5000, 5000), (3000, 8192)])
 def test_features_match_oracle(n, n_anchor):
     dwg = _dwg()
     c = synth.torus_ellipsoids(max(n, 64), seed=40)
@@ -30,8 +30,40 @@ def test_features_match_oracle(n, n_anchor):
     f = host(dwg.features(cuda(P), n_anchor))
     ref, amb = om.features(P, n_anchor)
     ok = ~amb
-    assert ok.mean() >= 0.98
+    print(f"[features] n={n} anchors={n_anchor} flagged {amb.mean():.4f} max err {np.max(np.abs(f[ok] - ref[ok])):.2e}")
     assert np.max(np.abs(f[ok] - ref[ok])) < 2e-4
+    # rows with near-equal neighbour distances: the GPU's 16 neighbours must be one of the
+    # orders and selections those ties allow
+    for i in np.flatnonzero(amb):
+        assert _tied_features_valid(P, n_anchor, i, f[i]), i
+
+
+def _tied_features_valid(P, n_anchor, i, fi, tol=2e-4):
+    """fi [48] is (a_k - p_i) / s for some 16 of p_i's 17 nearest anchors that a float32 search
+    could pick (only a candidate whose distance ties the 16th within 1e-5 relative may be
+    swapped out), in any order among equal distances."""
+    from scipy.optimize import linear_sum_assignment
+
+    import oracle
+    P = np.asarray(P, np.float64)
+    n = P.shape[1]
+    stride = max(1, n // n_anchor)
+    A = P[:, ::stride]
+    skip = np.array([i // stride if i % stride == 0 else -1], np.int32)
+    idx, dist = oracle.knn(A, P[:, i:i + 1], om.K + 1, skip=skip)
+    idx, dist = idx[0], dist[0]
+    got = fi.reshape(om.K, 3)
+    for drop in range(om.K + 1):
+        if drop < om.K and abs(dist[drop] - dist[om.K]) > 1e-5 * dist[om.K]:
+            continue  # dropping this one instead of the 17th is not a tie
+        keep = [k for k in range(om.K + 1) if k != drop]
+        s = dist[keep].mean()
+        want = ((A[:, idx[keep]] - P[:, i:i + 1]) / s).T
+        cost = np.linalg.norm(got[:, None, :] - want[None, :, :], axis=2)
+        r, c = linear_sum_assignment(cost)
+        if cost[r, c].max() < tol:
+            return True
+    return False
 
 
 def _weights(seed):
@@ -49,8 +81,16 @@ def test_mlp_forward_matches_oracle(B):
     X = rng.standard_normal((B, 48)).astype(np.float32)
     Y = host(dwg.mlp_infer(cuda(blob), cuda(X)))
     _, yhat, _ = om.forward(blob, X)
-    assert _rel_fro(Y, yhat) < 1e-2
+    assert _rel_fro(Y, yhat) < 1e-4
     ang = np.degrees(np.arccos(np.clip(np.sum(Y * yhat, axis=1), -1, 1)))
+    y, ybound = om.forward_bound(blob, X)
+    bound = np.degrees(np.arcsin(np.minimum(1.0, ybound / np.linalg.norm(y, axis=1))))
+    print(f"[mlp fwd] B={B} rel {_rel_fro(Y, yhat):.2e} angle p50 {np.median(ang):.2e} p99 {np.percentile(ang, 99):.2e} "
+          f"max {ang.max():.2e}; bound p50 {np.median(bound):.2e}")
+    # every row within the rigorous float32/BF16 bound of the oracle; and in practice within
+    # 0.1 deg (a one-ulp BF16 flip of an activation moves a row by ~0.02 deg)
+    assert np.all(ang <= bound + 1e-6)
+    assert ang.max() <= 0.1
     assert np.mean(ang < 1.0) > 0.99
 
 
@@ -72,10 +112,14 @@ def test_mlp_train_step_matches_oracle():
     assert abs(host(loss)[0] - rl) <= 1e-4 * max(1.0, abs(rl))
     g = host(g)
     off = 0
+    errs = {}
     for name, shp in om.SHAPES:
         k = int(np.prod(shp))
-        assert _rel_fro(g[off:off + k], rg[off:off + k]) < 2e-2, name
+        errs[name] = _rel_fro(g[off:off + k], rg[off:off + k])
         off += k
+    print("[mlp grad] " + " ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    for name, e in errs.items():
+        assert e < 1e-3, name  # measured <= 3.4e-5 (BF16 operands identical on both sides)
     # Adam at step 1 moves every parameter by -lr * g / (|g| + eps) (bias-corrected moments)
     step = host(p) - blob
     expect = -lr * g / (np.abs(g) + 1e-8)

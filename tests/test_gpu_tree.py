@@ -181,3 +181,27 @@ def test_tree_mode_is_deterministic():
     dwg.iterate(P, a, d, N1, prm, max_iters=3, fixed_iters=True)
     dwg.iterate(P, a, d, N2, prm, max_iters=3, fixed_iters=True)
     assert torch.equal(N1, N2)
+
+
+@pytest.mark.parametrize("n,leaf,qkind", [(20_000, 32, "points"), (20_000, 8, "points"), (50_000, 32, "box")])
+def test_traversal_work_matches_oracle(n, leaf, qkind):
+    """dwg_octree_work: the far dipoles and leaf pairs the GPU traversal takes, totalled over
+    the queries, equal the oracle's counts of the same decisions (the opening test is FP64 on
+    both sides; queries the oracle flags as within 1e-7 of an opening radius may decide
+    differently and are allowed one node's worth of difference each)."""
+    dwg = _dwg()
+    c = synth.torus_ellipsoids(n, seed=507)
+    d = oracle.anchor_delta(c.P).astype(np.float32)
+    rng = np.random.default_rng(8)
+    Q = c.P if qkind == "points" else rng.uniform(-1.6, 1.6, (3, 3000)).astype(np.float32)
+    prm = dwg.Params(lam=10.0, beta=2.3, leaf=leaf)
+    far, pairs = dwg.octree_work(cuda(c.P), cuda(c.area), cuda(d), cuda(Q) if qkind != "points" else cuda(c.P), prm)
+    _, _, fl, wk = oracle.tree_gwn(c.P, c.N_true, c.area, d, Q, lam=10.0, beta=2.3, leaf=leaf, grad=False,
+                                   work=True)
+    print(f"[tree work] n={n} leaf={leaf} {qkind}: far {far} pairs {pairs} (oracle {wk[:, 1].sum()} "
+          f"{wk[:, 2].sum()}), flagged {int(fl.sum())}")
+    nfl = int(fl.sum())
+    assert abs(far - int(wk[:, 1].sum())) <= 8 * nfl
+    assert abs(pairs - int(wk[:, 2].sum())) <= 8 * leaf * nfl
+    if nfl == 0:
+        assert far == int(wk[:, 1].sum()) and pairs == int(wk[:, 2].sum())
