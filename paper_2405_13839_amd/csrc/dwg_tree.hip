@@ -501,9 +501,11 @@ __global__ void k_tree_leafpos(const int4* __restrict__ node, const int32_t* __r
 // next node is usually i + 1 (a node opened, or a leaf, whose skip is i + 1), so its data is
 // loaded one step ahead.
 constexpr int kFoldLeaves = 4;
+// Threads per block of the traversal: its wavefronts share nothing (no LDS, no barrier).
+constexpr int kTreeBlock = 256;
 
 template <bool GRAD, bool SCREENED, bool KAHAN>
-__global__ __launch_bounds__(256) void k_tree_eval(const float* __restrict__ Q, int64_t m,
+__global__ __launch_bounds__(kTreeBlock) void k_tree_eval(const float* __restrict__ Q, int64_t m,
                                                    const int32_t* __restrict__ qperm, const int4* __restrict__ node,
                                                    const double4* __restrict__ geo, const float4* __restrict__ mom,
                                                    const int32_t* __restrict__ total_p, int64_t cap,
@@ -696,9 +698,9 @@ dwg_status scan_f64(const float4* src, int64_t n, const TreeWork& t, hipStream_t
 template <bool GRAD, bool SCREENED, bool KAHAN>
 void launch_eval_t(const float* Q, int64_t m, const int32_t* qperm, const GwnWork& w, const TreeWork& t,
                    float kappa, hipStream_t st) {
-  hipLaunchKernelGGL((k_tree_eval<GRAD, SCREENED, KAHAN>), dim3((unsigned)(w.mpad / 256)), dim3(256), 0, st, Q, m,
-                     qperm, t.node, t.geo, t.mom, t.off + t.n, t.cap, w.src, t.n, kScaledScr, kappa, w.part,
-                     w.mpad);
+  hipLaunchKernelGGL((k_tree_eval<GRAD, SCREENED, KAHAN>), dim3((unsigned)(w.mpad / kTreeBlock)), dim3(kTreeBlock), 0,
+                     st, Q, m, qperm, t.node, t.geo, t.mom, t.off + t.n, t.cap, w.src, t.n, kScaledScr, kappa,
+                     w.part, w.mpad);
 }
 
 }  // namespace
