@@ -529,10 +529,6 @@ __global__ __launch_bounds__(kTreeBlock) void k_tree_eval(const float* __restric
   double4 g = geo[0];
   float4 mm = mom[0];
   while (i < nn) {
-    const int nxt = i + 1 < nn ? i + 1 : i;
-    const int4 nd1 = node[nxt];
-    const double4 g1 = geo[nxt];
-    const float4 mm1 = mom[nxt];
     const int nskip = __builtin_amdgcn_readfirstlane(nd.z);
     bool open = false, direct = false;
     if (i >= skip_to) {
@@ -551,6 +547,16 @@ __global__ __launch_bounds__(kTreeBlock) void k_tree_eval(const float* __restric
         open = true;
       }
     }
+    // The next node is loaded only now: scalar loads return out of order, so the wait in
+    // front of this step's test covered every scalar load in flight; issued after the test,
+    // the next node's loads have the rest of this step to arrive. (Loading the node after
+    // this one's subtree too, the other possible successor, cost more registers than it
+    // saved.)
+    __asm__ __volatile__("" ::: "memory");
+    const int nxt = i + 1 < nn ? i + 1 : i;
+    const int4 nd1 = node[nxt];
+    const double4 g1 = geo[nxt];
+    const float4 mm1 = mom[nxt];
     int next;
     if (__any(open)) {
       next = i + 1;
@@ -561,10 +567,13 @@ __global__ __launch_bounds__(kTreeBlock) void k_tree_eval(const float* __restric
         if (s1 > n_src) s1 = (int)n_src;
         // the query relative to the leaf's centre, as its sources are staged (k_tree_leafpos)
         const float lx = kappa * (ux - (float)g.x), ly = kappa * (uy - (float)g.y), lz = kappa * (uz - (float)g.z);
-#pragma unroll 4
-        for (int j = s0; j < s1; ++j) {
-          const float4 a = src[2 * (int64_t)j], b = src[2 * (int64_t)j + 1];
-          if (direct) {
+        if (direct) {
+          // the lanes that did not open the leaf sit the whole loop out (one exec mask for the
+          // loop, not one per source); unrolling lengthened the loop without gain (leaves
+          // hold a few sources on average)
+#pragma unroll 1
+          for (int j = s0; j < s1; ++j) {
+            const float4 a = src[2 * (int64_t)j], b = src[2 * (int64_t)j + 1];
             if (SCREENED)
               pair_screened<GRAD, false>(a, b, lx, ly, lz, sk, acc);
             else
