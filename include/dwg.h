@@ -161,17 +161,24 @@ dwg_status dwg_octree(const float* P, int64_t n, int leaf, int32_t* perm, int32_
                       int64_t* count, void* ws, size_t ws_bytes, void* stream);
 
 /*
- * dwg_octree_work -- the work of the octree mode's traversal (Sec. 5.2) for m queries Q:
- * *far (HOST) = the number of (query, node) pairs the traversal takes as one dipole,
- * *pairs (HOST) = the number of (query, source) pairs it sums one by one at leaves, both
- * totalled over the queries. They depend on the positions, areas, radii and kp (the opening
+ * dwg_octree_work -- the work of the octree mode's traversal (Sec. 5.2) for m queries Q,
+ * written to work[0..3] (HOST), each totalled over the queries:
+ *   work[0] = (query, node) pairs the traversal takes as one dipole;
+ *   work[1] = (query, source) pairs it sums one by one at leaves;
+ *   work[2] = traversal steps at which at least one query of a wavefront (64 consecutive
+ *             queries in the spatial order the evaluation uses) takes the node as a dipole:
+ *             the evaluation runs the dipole arithmetic once per such step for all 64 lanes;
+ *   work[3] = source iterations of the wavefronts' leaf loops: at a leaf that at least one
+ *             of its queries opens, a wavefront runs one iteration per source of the leaf.
+ * work[0] / (64 work[2]) and work[1] / (64 work[3]) are the fractions of lanes doing useful
+ * work in those steps. The counts depend on the positions, areas, radii and kp (the opening
  * decisions), not on the normals. Synchronous. Requires kp->tree_beta > 0 and n < 2^30.
- * Workspace: dwg_workspace_bytes(n, m, kp). Errors as dwg_gwn_eval (*far and *pairs are set
- * to 0 first).
+ * Workspace: dwg_workspace_bytes(n, m, kp). Errors as dwg_gwn_eval (work[] is set to 0
+ * first).
  */
 dwg_status dwg_octree_work(const float* P, const float* area, const float* delta, int64_t n, const float* Q,
-                           int64_t m, const dwg_kernel_params* kp, int64_t* far, int64_t* pairs, void* ws,
-                           size_t ws_bytes, void* stream);
+                           int64_t m, const dwg_kernel_params* kp, int64_t* work, void* ws, size_t ws_bytes,
+                           void* stream);
 
 /* Grid of the level-set update (Sec. 4.3, Algorithm 1). */
 typedef struct dwg_mc_params {

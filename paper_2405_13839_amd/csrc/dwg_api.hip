@@ -335,11 +335,11 @@ dwg_status dwg_gwn_grad_static(const float* P, const float* N, const float* area
 }
 
 dwg_status dwg_octree_work(const float* P, const float* area, const float* delta, int64_t n, const float* Q,
-                           int64_t m, const dwg_kernel_params* kpp, int64_t* far, int64_t* pairs, void* ws,
-                           size_t ws_bytes, void* stream) {
-  if (far) *far = 0;
-  if (pairs) *pairs = 0;
-  DWG_CHECK(P && area && Q && far && pairs, "P, area, Q, far and pairs must not be NULL");
+                           int64_t m, const dwg_kernel_params* kpp, int64_t* work, void* ws, size_t ws_bytes,
+                           void* stream) {
+  if (work)
+    for (int k = 0; k < kTreeWorkCounts; ++k) work[k] = 0;
+  DWG_CHECK(P && area && Q && work, "P, area, Q and work must not be NULL");
   DWG_CHECK(n >= 1 && m >= 1, "n and m must be >= 1 (got n=%lld, m=%lld)", (long long)n, (long long)m);
   DWG_CHECK(n < (int64_t(1) << 30) && m < (int64_t(1) << 31), "need n < 2^30 and m < 2^31");
   DWG_PROPAGATE(check_kp(kpp));
@@ -348,7 +348,7 @@ dwg_status dwg_octree_work(const float* P, const float* area, const float* delta
   Carver need(nullptr);
   carve_gwn(need, n, m, 1, false, nullptr);
   carve_tree(need, n, tree_leaf(kp), kp.tree_beta, nullptr);
-  need.take<unsigned long long>(2);
+  need.take<unsigned long long>(kTreeWorkCounts);
   DWG_CHECK(ws || ws_bytes == 0, "ws is NULL but ws_bytes > 0");
   if (!ws || ws_bytes < need.used) {
     set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, need.used);
@@ -362,15 +362,14 @@ dwg_status dwg_octree_work(const float* P, const float* area, const float* delta
   TreeWork tw;
   carve_gwn(c, n, m, 1, same, &wk);
   carve_tree(c, n, tree_leaf(kp), kp.tree_beta, &tw);
-  unsigned long long* cnt = c.take<unsigned long long>(2);
+  unsigned long long* cnt = c.take<unsigned long long>(kTreeWorkCounts);
   DWG_PROPAGATE(tree_build(P, area, delta, n, kp.eps, tw, wk.perm_s, st));
   if (!same) DWG_PROPAGATE(spatial_sort(Q, m, nullptr, 0.0f, wk.sort, wk.perm_q, st));
   DWG_PROPAGATE(tree_work(Q, m, wk.perm_q, tw, cnt, st));
-  unsigned long long h[2] = {0, 0};
+  unsigned long long h[kTreeWorkCounts] = {};
   DWG_TRY_HIP(hipMemcpyAsync(h, cnt, sizeof h, hipMemcpyDeviceToHost, st));
   DWG_TRY_HIP(hipStreamSynchronize(st));
-  *far = (int64_t)h[0];
-  *pairs = (int64_t)h[1];
+  for (int k = 0; k < kTreeWorkCounts; ++k) work[k] = (int64_t)h[k];
   return DWG_OK;
 }
 

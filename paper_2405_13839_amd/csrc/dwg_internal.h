@@ -186,8 +186,10 @@ dwg_status tree_moments(const GwnWork& w, const TreeWork& t, hipStream_t st);
 // Octree-approximated w (and grad) at the sorted queries of w into w.part (split 1).
 dwg_status tree_eval(const float* Q, int64_t m, const dwg_kernel_params& kp, bool grad, const GwnWork& w,
                      const TreeWork& t, hipStream_t st);
-// Totals over the m sorted queries of the traversal's far dipoles (out[0]) and leaf pairs
-// (out[1]); out is 2 device counters.
+// Work of the traversal over the m sorted queries: far dipoles (out[0]), leaf pairs (out[1]),
+// wavefront steps with at least one far lane (out[2]) and wavefront leaf-loop iterations
+// (out[3]); out is kTreeWorkCounts device counters.
+constexpr int kTreeWorkCounts = 4;
 dwg_status tree_work(const float* Q, int64_t m, const int32_t* qperm, const TreeWork& t, unsigned long long* out,
                      hipStream_t st);
 dwg_status tree_export(const TreeWork& t, int32_t* nodes_out, int64_t cap_out, int64_t* count_host,

@@ -504,6 +504,16 @@ constexpr int kFoldLeaves = 4;
 // Threads per block of the traversal: its wavefronts share nothing (no LDS, no barrier).
 constexpr int kTreeBlock = 256;
 
+// Workgroups are dealt to the 8 XCDs in turn (block b to XCD b mod 8), and each XCD has an L2
+// of its own. Block b evaluates the (b mod 8)-th contiguous run of query blocks instead of
+// query block b, so the blocks resident on one XCD hold neighbouring queries, which visit
+// nearly the same nodes and leaf sources, and that XCD's L2 holds one region of the tree
+// rather than every eighth block's share of all of it. A bijection of [0, nb) onto itself.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
+  const unsigned q = nb / 8, r = nb % 8, x = b % 8, k = b / 8;
+  return x * q + (x < r ? x : r) + k;
+}
+
 template <bool GRAD, bool SCREENED, bool KAHAN>
 __global__ __launch_bounds__(kTreeBlock) void k_tree_eval(const float* __restrict__ Q, int64_t m,
                                                    const int32_t* __restrict__ qperm, const int4* __restrict__ node,
@@ -512,7 +522,7 @@ __global__ __launch_bounds__(kTreeBlock) void k_tree_eval(const float* __restric
                                                    const float4* __restrict__ src, int64_t n_src, Scr sk,
                                                    float kappa, float* __restrict__ part, int64_t mpad) {
   constexpr int NA = GRAD ? kNAcc : 1;
-  const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t qi = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t o = qperm[qi < m ? qi : m - 1];
   const float ux = Q[o], uy = Q[m + o], uz = Q[2 * m + o];
   const double dqx = ux, dqy = uy, dqz = uz;  // the opening test runs in unscaled FP64
@@ -605,34 +615,37 @@ __global__ __launch_bounds__(kTreeBlock) void k_tree_eval(const float* __restric
   for (int a = 0; a < NA; ++a) part[a * mpad + qi] = KAHAN ? sum[a] - cmp[a] : sum[a];
 }
 
-// Work of the traversal, totalled over the queries: far nodes taken as one dipole and source
-// pairs summed at leaves. The decisions are those of k_tree_eval (the same FP64 opening test,
-// the same wave-wide walk), without its arithmetic; lanes past m do not count. Integer atomics
+// Work of the traversal (the counts of dwg_octree_work). The decisions are those of
+// k_tree_eval (the same FP64 opening test, the same wave-wide walk over the same wavefronts of
+// 64 sorted queries), without its arithmetic. Per-query counts leave out lanes past m (they
+// repeat query m - 1, which sits in the same wavefront, so they change no wave-wide step);
+// wavefront counts come from lane 0 of each wavefront with a query below m. Integer atomics
 // make the totals independent of the order of the blocks.
 __global__ __launch_bounds__(256) void k_tree_work(const float* __restrict__ Q, int64_t m,
                                                    const int32_t* __restrict__ qperm, const int4* __restrict__ node,
                                                    const double4* __restrict__ geo,
                                                    const int32_t* __restrict__ total_p, int64_t cap, int64_t n_src,
                                                    unsigned long long* __restrict__ out) {
-  __shared__ unsigned long long red[2][4];
+  __shared__ unsigned long long red[kTreeWorkCounts][4];
   const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = qi < m;
   const int64_t o = qperm[live ? qi : m - 1];
   const double dqx = Q[o], dqy = Q[m + o], dqz = Q[2 * m + o];
   int nn = __builtin_amdgcn_readfirstlane(*total_p);
   if (nn > cap) nn = (int)cap;
-  unsigned long long nfar = 0, npair = 0;
+  unsigned long long nfar = 0, npair = 0, wfar = 0, wleaf = 0;
   int skip_to = 0;
   int i = 0;
   while (i < nn) {
     const int4 nd = node[i];
     const double4 g = geo[i];
     const int nskip = __builtin_amdgcn_readfirstlane(nd.z);
-    bool open = false, direct = false;
+    bool far = false, open = false, direct = false;
     if (i >= skip_to) {
       const double dx = g.x - dqx, dy = g.y - dqy, dz = g.z - dqz;
       const double d2 = dx * dx + dy * dy + dz * dz;
       if (d2 > g.w) {
+        far = true;
         ++nfar;
         skip_to = nskip;
       } else if (nd.w >> 8) {
@@ -641,14 +654,14 @@ __global__ __launch_bounds__(256) void k_tree_work(const float* __restrict__ Q, 
         open = true;
       }
     }
+    if (__any(far)) ++wfar;
     int next;
     if (__any(open)) {
       next = i + 1;
     } else {
-      if (direct) {
-        const int s1 = nd.y < n_src ? nd.y : (int)n_src;
-        npair += (unsigned long long)(s1 - nd.x);
-      }
+      const int s1 = nd.y < n_src ? nd.y : (int)n_src;
+      if (direct) npair += (unsigned long long)(s1 - nd.x);
+      if (__any(direct)) wleaf += (unsigned long long)(s1 - __builtin_amdgcn_readfirstlane(nd.x));
       next = nskip > i ? nskip : i + 1;
     }
     i = __builtin_amdgcn_readfirstlane(next);
@@ -660,18 +673,19 @@ __global__ __launch_bounds__(256) void k_tree_work(const float* __restrict__ Q, 
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (lane == 0) {
+    // lane 0 is live whenever any lane of its wavefront is
     red[0][wv] = nfar;
     red[1][wv] = npair;
+    red[2][wv] = live ? wfar : 0;
+    red[3][wv] = live ? wleaf : 0;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    atomicAdd(&out[0], red[0][0] + red[0][1] + red[0][2] + red[0][3]);
-    atomicAdd(&out[1], red[1][0] + red[1][1] + red[1][2] + red[1][3]);
-  }
+  if (threadIdx.x < kTreeWorkCounts)
+    atomicAdd(&out[threadIdx.x], red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3]);
 }
 
-__global__ void k_zero_u64x2(unsigned long long* __restrict__ a) {
-  if (threadIdx.x < 2) a[threadIdx.x] = 0ull;
+__global__ void k_zero_u64(unsigned long long* __restrict__ a, int k) {
+  if ((int)threadIdx.x < k) a[threadIdx.x] = 0ull;
 }
 
 __global__ void k_copy_i32(const int32_t* __restrict__ a, int64_t n, int32_t* __restrict__ b) {
@@ -861,7 +875,7 @@ dwg_status tree_eval(const float* Q, int64_t m, const dwg_kernel_params& kp, boo
 
 dwg_status tree_work(const float* Q, int64_t m, const int32_t* qperm, const TreeWork& t, unsigned long long* out,
                      hipStream_t st) {
-  hipLaunchKernelGGL(k_zero_u64x2, dim3(1), dim3(64), 0, st, out);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, out, kTreeWorkCounts);
   DWG_TRY_LAUNCH();
   hipLaunchKernelGGL(k_tree_work, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, st, Q, m, qperm, t.node, t.geo,
                      t.off + t.n, t.cap, t.n, out);

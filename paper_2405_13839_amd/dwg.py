@@ -72,8 +72,7 @@ def load():
     lib.dwg_gwn_eval.argtypes = [vp, vp, vp, vp, i64, vp, i64, kpp, vp, vp, vp, sz, vp]
     lib.dwg_gwn_grad.argtypes = [vp, vp, vp, vp, i64, vp, i64, kpp, vp, vp, vp, vp, sz, vp]
     lib.dwg_gwn_grad_static.argtypes = [vp, vp, vp, vp, i64, vp, i64, kpp, vp, vp, vp, vp]
-    lib.dwg_octree_work.argtypes = [vp, vp, vp, i64, vp, i64, kpp, ctypes.POINTER(i64), ctypes.POINTER(i64), vp,
-                                    sz, vp]
+    lib.dwg_octree_work.argtypes = [vp, vp, vp, i64, vp, i64, kpp, ctypes.POINTER(i64), vp, sz, vp]
     lib.dwg_iterate.argtypes = [vp, vp, vp, i64, vp, kpp, ctypes.POINTER(IterateParams),
                                 ctypes.POINTER(IterStat), ctypes.POINTER(ctypes.c_int), vp, sz, vp]
     lib.dwg_init_normals.argtypes = [i32, ctypes.c_uint64, vp, i64, vp, vp, vp, sz, vp]
@@ -405,8 +404,27 @@ def octree(P, leaf: int = 0, ws=None):
     return perm, nodes[:cnt.value]
 
 
-def octree_work(P, area, delta, Q, params: Params, ws=None):
-    """(far dipoles, leaf pairs) of the octree traversal for the queries Q, totalled."""
+@dataclass(frozen=True)
+class OctreeWork:
+    """Work of one octree evaluation, totalled over the queries (dwg_octree_work)."""
+    far: int         # (query, node) pairs taken as one dipole
+    pairs: int       # (query, source) pairs summed at leaves
+    far_steps: int   # wavefront steps with at least one query taking the node as a dipole
+    leaf_steps: int  # source iterations of the wavefronts' leaf loops
+
+    @property
+    def far_lanes(self) -> float:
+        """Fraction of the lanes of the far steps that add a dipole."""
+        return self.far / (64 * self.far_steps) if self.far_steps else 0.0
+
+    @property
+    def leaf_lanes(self) -> float:
+        """Fraction of the lanes of the leaf-loop iterations that add a pair."""
+        return self.pairs / (64 * self.leaf_steps) if self.leaf_steps else 0.0
+
+
+def octree_work(P, area, delta, Q, params: Params, ws=None) -> OctreeWork:
+    """Work of the octree traversal for the queries Q (decisions only, no arithmetic)."""
     lib = load()
     P = _pts(P, "P")
     n = P.shape[1]
@@ -419,10 +437,10 @@ def octree_work(P, area, delta, Q, params: Params, ws=None):
         ws = workspace(n, m, P.device, params)
     _dev(ws, "ws", dtype=torch.uint8, device=P.device)
     kp = params.c()
-    far, pairs = ctypes.c_int64(0), ctypes.c_int64(0)
+    work = (ctypes.c_int64 * 4)()
     _check(_run(P.device, lib.dwg_octree_work, _ptr(P), _ptr(area), _ptr(delta), n, _ptr(Q), m, ctypes.byref(kp),
-                ctypes.byref(far), ctypes.byref(pairs), _ptr(ws), ws.numel(), _stream(P.device)))
-    return far.value, pairs.value
+                work, _ptr(ws), ws.numel(), _stream(P.device)))
+    return OctreeWork(*(int(v) for v in work))
 
 
 def pca_normals(P, ws=None) -> torch.Tensor:

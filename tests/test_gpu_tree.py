@@ -195,7 +195,8 @@ def test_traversal_work_matches_oracle(n, leaf, qkind):
     rng = np.random.default_rng(8)
     Q = c.P if qkind == "points" else rng.uniform(-1.6, 1.6, (3, 3000)).astype(np.float32)
     prm = dwg.Params(lam=10.0, beta=2.3, leaf=leaf)
-    far, pairs = dwg.octree_work(cuda(c.P), cuda(c.area), cuda(d), cuda(Q) if qkind != "points" else cuda(c.P), prm)
+    wk_gpu = dwg.octree_work(cuda(c.P), cuda(c.area), cuda(d), cuda(Q) if qkind != "points" else cuda(c.P), prm)
+    far, pairs = wk_gpu.far, wk_gpu.pairs
     _, _, fl, wk = oracle.tree_gwn(c.P, c.N_true, c.area, d, Q, lam=10.0, beta=2.3, leaf=leaf, grad=False,
                                    work=True)
     print(f"[tree work] n={n} leaf={leaf} {qkind}: far {far} pairs {pairs} (oracle {wk[:, 1].sum()} "
@@ -205,3 +206,25 @@ def test_traversal_work_matches_oracle(n, leaf, qkind):
     assert abs(pairs - int(wk[:, 2].sum())) <= 8 * leaf * nfl
     if nfl == 0:
         assert far == int(wk[:, 1].sum()) and pairs == int(wk[:, 2].sum())
+    # a wavefront step serves at most 64 and at least one of its queries
+    assert wk_gpu.far_steps <= far <= 64 * wk_gpu.far_steps
+    assert wk_gpu.leaf_steps <= pairs <= 64 * wk_gpu.leaf_steps
+
+
+@pytest.mark.parametrize("m", [1, 64, 200])
+def test_traversal_wave_counts_of_one_repeated_query(m):
+    """m copies of one query: every lane of a wavefront takes the same decisions, so each
+    far step adds one dipole per query and each leaf iteration one pair per query; with m = 1
+    (63 lanes past m) the wavefront counts equal the per-query counts."""
+    dwg = _dwg()
+    c = synth.torus_ellipsoids(20_000, seed=508)
+    d = oracle.anchor_delta(c.P).astype(np.float32)
+    Q = np.repeat(np.array([[0.9], [0.05], [0.1]], np.float32), m, axis=1)
+    prm = dwg.Params(lam=10.0, beta=2.3, leaf=32)
+    wk = dwg.octree_work(cuda(c.P), cuda(c.area), cuda(d), cuda(Q), prm)
+    _, _, fl, wo = oracle.tree_gwn(c.P, c.N_true, c.area, d, Q[:, :1], lam=10.0, beta=2.3, leaf=32, grad=False,
+                                   work=True)
+    waves = -(-m // 64)
+    assert fl.sum() == 0
+    assert wk.far == m * int(wo[0, 1]) and wk.pairs == m * int(wo[0, 2])
+    assert wk.far_steps == waves * int(wo[0, 1]) and wk.leaf_steps == waves * int(wo[0, 2])
