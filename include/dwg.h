@@ -168,8 +168,10 @@ dwg_status dwg_octree(const float* P, int64_t n, int leaf, int32_t* perm, int32_
  *   work[2] = traversal steps at which at least one query of a wavefront (64 consecutive
  *             queries in the spatial order the evaluation uses) takes the node as a dipole:
  *             the evaluation runs the dipole arithmetic once per such step for all 64 lanes;
- *   work[3] = source iterations of the wavefronts' leaf loops: at a leaf that at least one
- *             of its queries opens, a wavefront runs one iteration per source of the leaf.
+ *   work[3] = source iterations of the wavefronts' leaf loops: at a leaf of s sources that
+ *             a of its queries open, a wavefront runs s iterations, or ceil(s / k) when the
+ *             evaluation spreads the leaf over k = 2^j groups of a lanes (k a <= 64, k <= s,
+ *             when that saves at least 2 iterations), each group taking every k-th source.
  * work[0] / (64 work[2]) and work[1] / (64 work[3]) are the fractions of lanes doing useful
  * work in those steps. The counts depend on the positions, areas, radii and kp (the opening
  * decisions), not on the normals. Synchronous. Requires kp->tree_beta > 0 and n < 2^30.

@@ -501,8 +501,22 @@ __global__ void k_tree_leafpos(const int4* __restrict__ node, const int32_t* __r
 // next node is usually i + 1 (a node opened, or a leaf, whose skip is i + 1), so its data is
 // loaded one step ahead.
 constexpr int kFoldLeaves = 4;
-// Threads per block of the traversal: its wavefronts share nothing (no LDS, no barrier).
+// Threads per block of the traversal: its wavefronts share no data and never wait for each
+// other (each has its own LDS area and no barrier).
 constexpr int kTreeBlock = 256;
+constexpr int kTreeWaves = kTreeBlock / 64;
+// A leaf visit is spread over the idle lanes when that saves at least this many iterations.
+constexpr int kSplitMinSaved = 2;
+
+// A leaf of ns sources opened by na lanes of a wavefront: the log2 of the number k of lane
+// groups its loop is spread over (0 = not spread), the largest power of two with k na <= 64
+// and k <= ns, kept only when ceil(ns / k) saves at least kSplitMinSaved iterations.
+__device__ __forceinline__ int leaf_split_log2(int na, int ns) {
+  int lk = 0;
+  while (lk < 6 && (na << (lk + 1)) <= 64 && (2 << lk) <= ns) ++lk;
+  if (lk > 0 && ns - ((ns + (1 << lk) - 1) >> lk) < kSplitMinSaved) lk = 0;
+  return lk;
+}
 
 // Workgroups are dealt to the 8 XCDs in turn (block b to XCD b mod 8), and each XCD has an L2
 // of its own. Block b evaluates the (b mod 8)-th contiguous run of query blocks instead of
@@ -522,6 +536,10 @@ __global__ __launch_bounds__(kTreeBlock) void k_tree_eval(const float* __restric
                                                    const float4* __restrict__ src, int64_t n_src, Scr sk,
                                                    float kappa, float* __restrict__ part, int64_t mpad) {
   constexpr int NA = GRAD ? kNAcc : 1;
+  // per wavefront: the queries of a split leaf visit by rank, and the lanes' partial sums
+  __shared__ float4 lds_q[kTreeWaves][64];
+  __shared__ float lds_p[kTreeWaves][64][NA == 1 ? 1 : 8];
+  const int wv = (int)(threadIdx.x >> 6);
   const int64_t qi = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t o = qperm[qi < m ? qi : m - 1];
   const float ux = Q[o], uy = Q[m + o], uz = Q[2 * m + o];
@@ -577,18 +595,66 @@ __global__ __launch_bounds__(kTreeBlock) void k_tree_eval(const float* __restric
         if (s1 > n_src) s1 = (int)n_src;
         // the query relative to the leaf's centre, as its sources are staged (k_tree_leafpos)
         const float lx = kappa * (ux - (float)g.x), ly = kappa * (uy - (float)g.y), lz = kappa * (uz - (float)g.z);
-        if (direct) {
-          // the lanes that did not open the leaf sit the whole loop out (one exec mask for the
-          // loop, not one per source); unrolling lengthened the loop without gain (leaves
-          // hold a few sources on average)
+        // With a lanes opening the leaf, k = 2^lk groups of a lanes (k a <= 64) can take an
+        // interleaved k-th of its sources each for one query, in ceil(s / k) iterations
+        // instead of s; the groups' partial sums then go back to the querying lanes.
+        const uint64_t dmask = __ballot(direct);
+        const int lk = __builtin_amdgcn_readfirstlane(leaf_split_log2(__popcll(dmask), s1 - s0));
+        if (lk == 0) {
+          if (direct) {
+            // the lanes that did not open the leaf sit the whole loop out (one exec mask for
+            // the loop, not one per source); unrolling lengthened the loop without gain
+            // (leaves hold a few sources on average)
 #pragma unroll 1
-          for (int j = s0; j < s1; ++j) {
-            const float4 a = src[2 * (int64_t)j], b = src[2 * (int64_t)j + 1];
-            if (SCREENED)
-              pair_screened<GRAD, false>(a, b, lx, ly, lz, sk, acc);
-            else
-              pair_plain<GRAD, false>(a, b, lx, ly, lz, acc);
+            for (int j = s0; j < s1; ++j) {
+              const float4 a = src[2 * (int64_t)j], b = src[2 * (int64_t)j + 1];
+              if (SCREENED)
+                pair_screened<GRAD, false>(a, b, lx, ly, lz, sk, acc);
+              else
+                pair_plain<GRAD, false>(a, b, lx, ly, lz, acc);
+            }
           }
+        } else {
+          const int lane = (int)(threadIdx.x & 63);
+          const int rank = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(dmask >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((unsigned)dmask, 0u));
+          float4* qs = lds_q[wv];
+          if (direct) qs[rank] = make_float4(lx, ly, lz, 0.0f);
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          const int grp = lane & ((1 << lk) - 1), who = lane >> lk;
+          float pac[NA];
+#pragma unroll
+          for (int a = 0; a < NA; ++a) pac[a] = 0.0f;
+          if (who < __popcll(dmask)) {
+            const float4 qq = qs[who];
+#pragma unroll 1
+            for (int j = s0 + grp; j < s1; j += 1 << lk) {
+              const float4 a = src[2 * (int64_t)j], b = src[2 * (int64_t)j + 1];
+              if (SCREENED)
+                pair_screened<GRAD, false>(a, b, qq.x, qq.y, qq.z, sk, pac);
+              else
+                pair_plain<GRAD, false>(a, b, qq.x, qq.y, qq.z, pac);
+            }
+          }
+          float* ps = lds_p[wv][lane];
+#pragma unroll
+          for (int a = 0; a < NA; ++a) ps[a] = pac[a];
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          if (direct) {
+#pragma unroll 1
+            for (int gi = 0; gi < (1 << lk); ++gi) {
+              const float* pg = lds_p[wv][(rank << lk) + gi];
+#pragma unroll
+              for (int a = 0; a < NA; ++a) acc[a] += pg[a];
+            }
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
         if (++visits == kFoldLeaves) {
           visits = 0;
@@ -661,7 +727,12 @@ __global__ __launch_bounds__(256) void k_tree_work(const float* __restrict__ Q, 
     } else {
       const int s1 = nd.y < n_src ? nd.y : (int)n_src;
       if (direct) npair += (unsigned long long)(s1 - nd.x);
-      if (__any(direct)) wleaf += (unsigned long long)(s1 - __builtin_amdgcn_readfirstlane(nd.x));
+      const uint64_t dmask = __ballot(direct);
+      if (dmask) {
+        const int ns = s1 - __builtin_amdgcn_readfirstlane(nd.x);
+        const int lk = leaf_split_log2(__popcll(dmask), ns);
+        wleaf += (unsigned long long)((ns + (1 << lk) - 1) >> lk);
+      }
       next = nskip > i ? nskip : i + 1;
     }
     i = __builtin_amdgcn_readfirstlane(next);

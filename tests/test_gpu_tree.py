@@ -86,6 +86,30 @@ def test_tree_gwn_matches_oracle(gen, lam, use_delta, comp, beta, leaf, nq):
     assert ew <= TOL_W and eg <= TOL_G
 
 
+@pytest.mark.parametrize("m", [2, 5, 40])
+def test_tree_sparse_wavefront_leaves_match_oracle(m):
+    """A leaf opened by at most half of a wavefront's lanes is spread over the idle lanes:
+    k groups of lanes (k a power of two, k x lanes <= 64) each take every k-th source for one
+    query, and the partial sums return to the querying lanes through LDS. m queries at
+    scattered points put a single lane on most leaves (the lanes past m repeat the last
+    query), so the spread loop runs with up to 32 groups; w and grad w match the oracle, and
+    with m = 2 the wavefront needs fewer leaf iterations than the live queries have pairs."""
+    dwg = _dwg()
+    c = synth.torus_ellipsoids(20_000, seed=509)
+    rng = np.random.default_rng(13)
+    N = unit_rows(rng, c.n)
+    d = oracle.anchor_delta(c.P).astype(np.float32)
+    Q = np.ascontiguousarray(c.P[:, np.sort(rng.choice(c.n, m, replace=False))])
+    prm = dwg.Params(lam=10.0, beta=2.3, leaf=32)
+    w, g = dwg.gwn(cuda(c.P), cuda(N), cuda(c.area), cuda(d), cuda(Q), prm)
+    w_ref, g_ref, flag = oracle.tree_gwn(c.P, N, c.area, d, Q, lam=10.0, beta=2.3, leaf=32)
+    ok = flag == 0
+    assert e_w(host(w)[ok], w_ref[ok]) <= TOL_W and e_g(host(g)[:, ok], g_ref[:, ok]) <= TOL_G
+    if m == 2:
+        wk = dwg.octree_work(cuda(c.P), cuda(c.area), cuda(d), cuda(Q), prm)
+        assert wk.leaf_steps < wk.pairs
+
+
 def test_tree_huge_beta_is_the_all_pairs_sum():
     """beta = 1e30 opens every node: the octree kernel then sums every source one by one."""
     dwg = _dwg()
