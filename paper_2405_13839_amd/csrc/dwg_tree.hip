@@ -32,6 +32,8 @@
 // wave descends (i + 1) when any active lane must open node i, sums a leaf's sources for the
 // lanes that opened it, and otherwise jumps to skip. Every query thus sees exactly the
 // per-query decisions of the paper's depth-first traversal; node loads are wave-uniform.
+// A leaf opened by at most half of the lanes is spread over the idle ones (groups of lanes
+// each take every k-th source for one query; partial sums return through LDS).
 // The FP64 criterion |q - c.m|^2 > crit^2 decides (unscaled); the far dipole and the leaf
 // pairs use the FP32 pair arithmetic of the all-pairs kernel in its scaled coordinates (leaf
 // pairs from positions staged relative to the leaf's centre).
@@ -512,10 +514,12 @@ constexpr int kSplitMinSaved = 2;
 // groups its loop is spread over (0 = not spread), the largest power of two with k na <= 64
 // and k <= ns, kept only when ceil(ns / k) saves at least kSplitMinSaved iterations.
 __device__ __forceinline__ int leaf_split_log2(int na, int ns) {
-  int lk = 0;
-  while (lk < 6 && (na << (lk + 1)) <= 64 && (2 << lk) <= ns) ++lk;
+  if (na < 1 || ns < 2) return 0;
+  const int by_lanes = __clz((unsigned)(na - 1)) - 26;  // 6 - ceil(log2 na): 2^j na <= 64
+  const int by_sources = 31 - __clz((unsigned)ns);      // floor(log2 ns): 2^j <= ns
+  int lk = by_lanes < by_sources ? by_lanes : by_sources;
   if (lk > 0 && ns - ((ns + (1 << lk) - 1) >> lk) < kSplitMinSaved) lk = 0;
-  return lk;
+  return lk > 0 ? lk : 0;
 }
 
 // Workgroups are dealt to the 8 XCDs in turn (block b to XCD b mod 8), and each XCD has an L2
