@@ -1,7 +1,8 @@
 """Pins of the octree oracle (Sec. 5.2 "Octree Traversal") against facts that do not come
 from its own code: the exact all-pairs sum (an opening radius that opens every node), an
 octree built by explicit geometric subdivision, the far-field error falling with the
-opening factor, and the area-weighted dipole of a far cluster."""
+opening factor and staying within the first-order remainder bound of its far dipoles, and
+the area-weighted dipole of a far cluster."""
 import math
 
 import numpy as np
@@ -156,3 +157,92 @@ def test_traversal_work_partitions_the_sources():
     _, _, _, wk = oracle.tree_gwn(c.P, c.N_true, c.area, d, Q[:, :20], beta=1e9, leaf=16, grad=False, work=True)
     np.testing.assert_array_equal(wk[:, 2] + wk[:, 3], c.n)
     np.testing.assert_array_equal(wk[:, 1], wk[:, 3])
+
+
+def _far_remainder_bounds(P, N, a, Q, beta, leaf):
+    """Per query, bounds on |w_tree - w| and |grad_tree - grad w| (plain kernel, no clamp
+    radius) from the node list, and the size of the far terms themselves: a far node
+    replaces its sources' dipoles m_j at p_j by their sum M at the area-weighted centre c.
+    Along the segment from c to p_j the source stays in the node's ball (radius
+    r = max |p_j - c|), at distance >= d - r from q (d = |c - q| > beta r). For
+    K(x) = m.x / (4 pi |x|^3), |grad_x K| <= 4|m| / (4 pi |x|^3) and the Hessian's norm is
+    <= 24|m| / (4 pi |x|^4), so the node's error in w is at most S / (pi (d - r)^3) and in
+    grad w at most 6 S / (pi (d - r)^4), S = sum |m_j| |p_j - c|. The far terms' size is
+    sum |M.(c - q)| / (4 pi d^3). The traversal (open a node unless |q - c| > crit =
+    max(beta r, r)) is redone here from the oracle's node list."""
+    P = np.asarray(P, np.float64)
+    N = np.asarray(N, np.float64)
+    a = np.asarray(a, np.float64)
+    perm, info = oracle.octree(P, leaf)
+    nn = len(info)
+    C = np.zeros((nn, 3))
+    M = np.zeros((nn, 3))
+    R = np.zeros(nn)
+    S = np.zeros(nn)
+    for k, (s, e, _, _) in enumerate(info):
+        idx = perm[s:e]
+        ak = a[idx]
+        c = (P[:, idx] * ak).sum(axis=1) / ak.sum()
+        dist = np.linalg.norm(P[:, idx] - c[:, None], axis=0)
+        m = N[:, idx] * ak
+        C[k], M[k], R[k], S[k] = c, m.sum(axis=1), dist.max(), (np.linalg.norm(m, axis=0) * dist).sum()
+    crit = np.maximum(beta * R, R)
+    bw = np.zeros(Q.shape[1])
+    bg = np.zeros(Q.shape[1])
+    far = np.zeros(Q.shape[1])
+    nfar = np.zeros(Q.shape[1], np.int64)
+    for i in range(Q.shape[1]):
+        q = np.asarray(Q[:, i], np.float64)
+        stack = [0]
+        while stack:
+            k = stack.pop()
+            x = C[k] - q
+            d = np.linalg.norm(x)
+            if d > crit[k]:
+                nfar[i] += 1
+                bw[i] += S[k] / (math.pi * (d - R[k]) ** 3)
+                bg[i] += 6.0 * S[k] / (math.pi * (d - R[k]) ** 4)
+                far[i] += abs(M[k] @ x) / (4 * math.pi * d ** 3)
+            elif info[k][3] != k + 1:  # not a leaf: its children follow it in pre-order
+                c = k + 1
+                while c < info[k][3]:
+                    stack.append(c)
+                    c = info[c][3]
+    return bw, bg, far, nfar
+
+
+def _remainder_case(shape, beta):
+    if shape == "sphere":
+        c = synth.fibonacci_sphere(4000)
+        P, N, a = c.P, c.N_true, c.area
+    else:
+        P, N, a, _ = _cloud(4000, 21)
+    rng = np.random.default_rng(5)
+    Q = np.concatenate([np.asarray(P[:, ::40], np.float64), rng.uniform(-1.5, 1.5, (3, 60))], axis=1)
+    w, g, _ = oracle.gwn(P, N, a, None, Q)
+    wt, gt, fl = oracle.tree_gwn(P, N, a, None, Q, beta=beta, leaf=8)
+    bw, bg, far, nfar = _far_remainder_bounds(P, N, a, Q, beta, 8)
+    ok = fl == 0
+    return w, g, wt, gt, ok, bw, bg, far, nfar
+
+
+@pytest.mark.parametrize("beta", [2.3, 16.0])
+@pytest.mark.parametrize("shape", ["sphere", "random_normals"])
+def test_tree_error_within_the_far_remainder_bound(shape, beta):
+    """The octree value differs from the exact all-pairs sum by no more than the first-order
+    remainder of its far dipoles (bound derived in _far_remainder_bounds), for w and grad w at
+    every query the oracle does not flag (observed: within 1-5% of the bound)."""
+    w, g, wt, gt, ok, bw, bg, far, nfar = _remainder_case(shape, beta)
+    assert ok.mean() > 0.95 and (nfar[ok] > 0).all()
+    ew = np.abs(wt - w)[ok]
+    eg = np.linalg.norm(gt - g, axis=0)[ok]
+    assert (ew <= bw[ok] * (1 + 1e-9) + 1e-13).all(), (ew / bw[ok]).max()
+    assert (eg <= bg[ok] * (1 + 1e-9) + 1e-12).all(), (eg / bg[ok]).max()
+
+
+def test_far_remainder_bound_is_below_the_far_field():
+    """The bound above is a pin, not a formality: with exact outward normals and beta = 16
+    it is several times smaller than the far terms themselves, so far dipoles with a wrong
+    sign, a wrong scale or left out would exceed it."""
+    w, g, wt, gt, ok, bw, bg, far, nfar = _remainder_case("sphere", 16.0)
+    assert np.median(bw[ok]) < 0.25 * np.median(far[ok])
