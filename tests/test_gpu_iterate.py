@@ -202,6 +202,26 @@ def test_knn_degenerate_reference_sets(shape):
     np.testing.assert_allclose(true_d, rdist, rtol=2e-6, atol=1e-7)
 
 
+def test_knn_cluster_with_far_outlier():
+    """40K references within ~1e-3 of a centre plus one at (1000, 1000, 1000): the grid's
+    cell size follows the bounding box, so all but one reference share one cell and every
+    query scans it whole (quadratic in the cell's occupancy, exact); the self 10-NN and the
+    10-NN radius still match the oracle, the outlier's included."""
+    dwg = _dwg()
+    rng = np.random.default_rng(23)
+    n = 40_000
+    P = rng.normal(0, 1e-3, (3, n))
+    P[:, 0] = 1000.0
+    P = P.astype(np.float32)
+    Pc = cuda(P)
+    idx, dist = dwg.knn(Pc, Pc, 10, self_skip=True)
+    sel = np.concatenate([[0], rng.choice(np.arange(1, n), 255, replace=False)])
+    _, rdist = oracle.knn(P, P[:, sel], 10, skip=sel)
+    np.testing.assert_allclose(host(dist)[sel].astype(np.float64), rdist, rtol=2e-6, atol=1e-9)
+    delta = host(dwg.delta_knn_mean(Pc, 10))
+    np.testing.assert_allclose(delta[sel].astype(np.float64), rdist.mean(axis=1), rtol=1e-5, atol=1e-9)
+
+
 def test_knn_self_full_size_sampled():
     """Self 15-NN at 1M points (the Voronoi-area configuration of the benchmark cloud, 5%
     outliers); 2000 sampled queries recomputed by the oracle."""
