@@ -61,13 +61,16 @@ int choose_split(int64_t n_src, int64_t n_qry, int requested);
 
 // Uniform grid over a reference point set (dwg_knn.hip).
 struct GridParams {
-  float ox, oy, oz;  // origin (bbox min)
+  float ox, oy, oz;  // origin (minimum corner of the trimmed box)
   float h, ih;       // cell size and its inverse
   int nx, ny, nz;
   int64_t ncells;
 };
 struct KnnWork {
   float* bbox_part;  // [256 * 6] per-block bbox partials
+  double* range;     // [6] trimmed box per axis (lo, hi)
+  int64_t* below;    // [3] reference points under each axis' lo
+  int32_t* hist;     // [3 * 1024] axis histograms of the trimming passes
   GridParams* gp;
   int32_t* key;      // [nr] cell of each reference point
   int32_t* start;    // [max_cells + 1] first sorted slot of each cell

@@ -2,10 +2,15 @@
 // "Poisson Kernels": mean distance to the k nearest neighbours) and the k = 16 anchor
 // features of the learned initial normals.
 //
-// Grid build: bounding box (deterministic two-stage min/max), cell size from the box
+// Grid build: bounding box (deterministic two-stage min/max), trimmed per axis to the
+// quantiles 1/1024 and 1 - 1/1024 of the reference points (three passes of a 1024-bin
+// histogram, each refining the range the last one found), cell size from the trimmed box's
 // volume with at most ~8 cells per reference point, counting sort of the reference points
 // by cell (atomic cursors; the order inside a cell is arbitrary, which is harmless because
-// candidates are ranked by the pair (squared distance, index)). Query: Chebyshev rings of
+// candidates are ranked by the pair (squared distance, index)). Points outside the trimmed
+// box sit in its border cells: a few points far from the rest then no longer stretch the
+// cells until the whole cloud shares one, and the search stays exact because projecting
+// onto a box shortens no distance (see k_knn). Query: Chebyshev rings of
 // cells around the query's own cell, a row of cells (one contiguous range of the sorted
 // points) at a time, keeping the k best candidates in registers, until the k-th best
 // distance is below the distance to the next ring. One thread per query takes rings 0..3;
@@ -68,20 +73,132 @@ __global__ void k_bbox_final(const float* __restrict__ part, int nblocks, float*
   }
 }
 
-// Final bbox and grid parameters (single thread; nblocks is small).
-__global__ void k_grid_params(const float* __restrict__ part, int nblocks, int64_t n,
-                              int64_t max_cells, GridParams* __restrict__ gp) {
-  if (threadIdx.x != 0) return;
-  float mn[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, mx[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
-  for (int b = 0; b < nblocks; ++b)
+// Grid box trimming. range[2d], range[2d + 1] = the current [lo, hi] of axis d (FP64) and
+// below[d] = the number of reference points under lo; kTrimLevels passes of k_axis_hist /
+// k_trim_refine narrow each axis to the bins that hold the ranks floor(n / 1024) and
+// n - 1 - floor(n / 1024) of its coordinates.
+constexpr int kTrimBins = 1024;
+constexpr int kTrimLevels = 3;
+
+// range = the bounding box (from the per-block partials, reduced by one block of 256
+// threads), below = 0, histograms cleared.
+__global__ __launch_bounds__(256) void k_trim_init(const float* __restrict__ part, int nblocks,
+                                                   double* __restrict__ range, int64_t* __restrict__ below,
+                                                   int32_t* __restrict__ hist) {
+  __shared__ float lds[6][256];
+  for (int i = threadIdx.x; i < 3 * kTrimBins; i += blockDim.x) hist[i] = 0;
+  float v[6] = {FLT_MAX, FLT_MAX, FLT_MAX, -FLT_MAX, -FLT_MAX, -FLT_MAX};
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
     for (int d = 0; d < 3; ++d) {
-      mn[d] = fminf(mn[d], part[b * 6 + d]);
-      mx[d] = fmaxf(mx[d], part[b * 6 + 3 + d]);
+      v[d] = fminf(v[d], part[b * 6 + d]);
+      v[3 + d] = fmaxf(v[3 + d], part[b * 6 + 3 + d]);
     }
+  for (int d = 0; d < 6; ++d) lds[d][threadIdx.x] = v[d];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int d = 0; d < 3; ++d) {
+        lds[d][threadIdx.x] = fminf(lds[d][threadIdx.x], lds[d][threadIdx.x + st]);
+        lds[3 + d][threadIdx.x] = fmaxf(lds[3 + d][threadIdx.x], lds[3 + d][threadIdx.x + st]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) {
+    range[2 * threadIdx.x] = lds[threadIdx.x][0];
+    range[2 * threadIdx.x + 1] = lds[3 + threadIdx.x][0];
+    below[threadIdx.x] = 0;
+  }
+}
+
+// Per axis, the histogram of the coordinates inside [lo, hi] over kTrimBins equal bins
+// (LDS counts per block, then added to `hist`); NaN coordinates fall in no bin.
+__global__ __launch_bounds__(256) void k_axis_hist(const float* __restrict__ R, int64_t n,
+                                                   const double* __restrict__ range, int32_t* __restrict__ hist) {
+  __shared__ int32_t h[3 * kTrimBins];
+  for (int i = threadIdx.x; i < 3 * kTrimBins; i += blockDim.x) h[i] = 0;
+  double lo[3], hi[3], sc[3];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = range[2 * d];
+    hi[d] = range[2 * d + 1];
+    sc[d] = hi[d] > lo[d] ? kTrimBins / (hi[d] - lo[d]) : 0.0;
+  }
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    for (int d = 0; d < 3; ++d) {
+      const double x = R[d * n + i];
+      if (x >= lo[d] && x <= hi[d]) {
+        int b = (int)((x - lo[d]) * sc[d]);
+        b = b < kTrimBins - 1 ? b : kTrimBins - 1;
+        atomicAdd(&h[d * kTrimBins + b], 1);
+      }
+    }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 3 * kTrimBins; i += blockDim.x)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// One block of 256 threads per axis (blockIdx.x): the bins holding ranks rlo and rhi
+// (counting the points below lo) become the new range, found from an exclusive scan of the
+// histogram in LDS; the histogram is cleared for the next pass. A range whose ranks are not
+// found (NaN coordinates among the points) is kept.
+__global__ __launch_bounds__(256) void k_trim_refine(int32_t* __restrict__ hist, double* __restrict__ range,
+                                                     int64_t* __restrict__ below, int64_t rlo, int64_t rhi) {
+  constexpr int kPer = kTrimBins / 256;
+  __shared__ int64_t scan[256];
+  __shared__ int found[2];
+  __shared__ int64_t below_lo;
+  const int d = blockIdx.x, t = threadIdx.x;
+  int32_t* hd = hist + d * kTrimBins;
+  int64_t c[kPer], sum = 0;
+  for (int k = 0; k < kPer; ++k) {
+    c[k] = hd[t * kPer + k];
+    hd[t * kPer + k] = 0;
+    sum += c[k];
+  }
+  scan[t] = sum;
+  if (t < 2) found[t] = -1;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {  // inclusive scan of the per-thread sums
+    const int64_t x = t >= off ? scan[t - off] : 0;
+    __syncthreads();
+    scan[t] += x;
+    __syncthreads();
+  }
+  int64_t cum = below[d] + scan[t] - sum;  // points below this thread's first bin
+  for (int k = 0; k < kPer; ++k) {
+    if (cum <= rlo && cum + c[k] > rlo) {
+      found[0] = t * kPer + k;
+      below_lo = cum;
+    }
+    if (cum <= rhi && cum + c[k] > rhi) found[1] = t * kPer + k;
+    cum += c[k];
+  }
+  __syncthreads();
+  if (t != 0) return;
+  const double lo = range[2 * d], hi = range[2 * d + 1];
+  const int blo = found[0], bhi = found[1];
+  if (blo < 0 || bhi < 0 || !(hi > lo)) return;
+  const double w = (hi - lo) / kTrimBins;
+  range[2 * d] = lo + blo * w;
+  range[2 * d + 1] = bhi == kTrimBins - 1 ? hi : lo + (bhi + 1) * w;
+  below[d] = below_lo;
+}
+
+// Grid parameters over the trimmed box (single thread).
+__global__ void k_grid_params(const double* __restrict__ range, int64_t max_cells, GridParams* __restrict__ gp) {
+  if (threadIdx.x != 0) return;
+  float mn[3], mx[3];
+  for (int d = 0; d < 3; ++d) {  // the FP64 range rounded outwards to FP32
+    mn[d] = (float)range[2 * d];
+    if ((double)mn[d] > range[2 * d]) mn[d] = nextafterf(mn[d], -INFINITY);
+    mx[d] = (float)range[2 * d + 1];
+    if ((double)mx[d] < range[2 * d + 1]) mx[d] = nextafterf(mx[d], INFINITY);
+  }
   double ext[3];
   double emax = 0.0;
   for (int d = 0; d < 3; ++d) {
     ext[d] = (double)mx[d] - (double)mn[d];
+    if (!(ext[d] >= 0.0 && ext[d] <= 1e30)) ext[d] = 1e30;  // infinite or NaN coordinates
     emax = fmax(emax, ext[d]);
   }
   if (!(emax > 0.0)) emax = 1.0;
@@ -89,10 +206,10 @@ __global__ void k_grid_params(const float* __restrict__ part, int nblocks, int64
   double vol = 1.0;
   for (int d = 0; d < 3; ++d) vol *= fmax(ext[d], 1e-3 * emax);
   double h = cbrt(vol / (double)max_cells);
-  // every point must fall inside the grid (no clamping of interior points): grow h until
-  // the uncapped cell counts multiply to at most max_cells
-  double dd[3];
-  for (;;) {
+  // every point of the box must fall inside the grid: grow h until the uncapped cell counts
+  // multiply to at most max_cells (at most a few steps; the cap only bounds the loop)
+  double dd[3] = {1.0, 1.0, 1.0};
+  for (int it = 0; it < 4096; ++it) {
     double cells = 1.0;
     for (int d = 0; d < 3; ++d) {
       dd[d] = floor(ext[d] / h) + 1.0;
@@ -100,6 +217,10 @@ __global__ void k_grid_params(const float* __restrict__ part, int nblocks, int64
     }
     if (cells <= (double)max_cells) break;
     h *= 1.05;
+  }
+  if (dd[0] * dd[1] * dd[2] > (double)max_cells) {  // not reached for finite extents; one cell
+    dd[0] = dd[1] = dd[2] = 1.0;
+    h = emax;
   }
   int dims[3] = {(int)dd[0], (int)dd[1], (int)dd[2]};
   GridParams g;
@@ -117,9 +238,11 @@ __global__ void k_grid_params(const float* __restrict__ part, int nblocks, int64
 
 __device__ __forceinline__ void cell_of(const GridParams& g, float x, float y, float z, int& cx,
                                         int& cy, int& cz) {
-  cx = min(max((int)floorf((x - g.ox) * g.ih), 0), g.nx - 1);
-  cy = min(max((int)floorf((y - g.oy) * g.ih), 0), g.ny - 1);
-  cz = min(max((int)floorf((z - g.oz) * g.ih), 0), g.nz - 1);
+  // clamped as floats before the conversion, so that points far outside the box (and NaN,
+  // which fmaxf maps to 0) land in its border cells
+  cx = (int)fminf(fmaxf(floorf((x - g.ox) * g.ih), 0.0f), (float)(g.nx - 1));
+  cy = (int)fminf(fmaxf(floorf((y - g.oy) * g.ih), 0.0f), (float)(g.ny - 1));
+  cz = (int)fminf(fmaxf(floorf((z - g.oz) * g.ih), 0.0f), (float)(g.nz - 1));
 }
 
 __global__ void k_zero_i32(int32_t* __restrict__ a, int64_t n) {
@@ -332,7 +455,9 @@ __global__ __launch_bounds__(256) void k_knn(const float* __restrict__ Q, int64_
   const int rmax = max(g.nx, max(g.ny, g.nz));
   // Rings 0..rcap, a row of cells at a time (ring_row). Every point outside the cube of
   // half-width r lies more than r h from the query, which ends the search once the k-th best
-  // distance is within r h; the cube of half-width rmax holds the whole grid.
+  // distance is within r h; the cube of half-width rmax holds the whole grid. (A point, or
+  // the query, outside the grid's box sits in the border cell that holds its projection onto
+  // the box; projecting both onto the box shortens no distance, so the bound still holds.)
   bool done = false;
   const int rlim = min(rcap, rmax);
   for (int r = 0; r <= rlim; ++r) {
@@ -795,7 +920,16 @@ dwg_status build_grid(const float* R, int64_t nr, const KnnWork& w, hipStream_t 
   const int64_t mc = max_cells_for(nr);
   hipLaunchKernelGGL(k_bbox_partial, dim3(kBboxBlocks), dim3(256), 0, st, R, nr, w.bbox_part);
   DWG_TRY_LAUNCH();
-  hipLaunchKernelGGL(k_grid_params, dim3(1), dim3(64), 0, st, w.bbox_part, kBboxBlocks, nr, mc, w.gp);
+  hipLaunchKernelGGL(k_trim_init, dim3(1), dim3(256), 0, st, w.bbox_part, kBboxBlocks, w.range, w.below, w.hist);
+  DWG_TRY_LAUNCH();
+  const int64_t rlo = nr / 1024, rhi = nr - 1 - nr / 1024;
+  for (int level = 0; level < kTrimLevels; ++level) {
+    hipLaunchKernelGGL(k_axis_hist, dim3(grid_for(nr, 256, 1024)), dim3(256), 0, st, R, nr, w.range, w.hist);
+    DWG_TRY_LAUNCH();
+    hipLaunchKernelGGL(k_trim_refine, dim3(3), dim3(256), 0, st, w.hist, w.range, w.below, rlo, rhi);
+    DWG_TRY_LAUNCH();
+  }
+  hipLaunchKernelGGL(k_grid_params, dim3(1), dim3(64), 0, st, w.range, mc, w.gp);
   DWG_TRY_LAUNCH();
   // counts and cursors over the largest possible grid (the actual grid has <= mc cells)
   hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(mc + 1)), dim3(256), 0, st, w.start, mc + 1);
@@ -853,6 +987,9 @@ size_t carve_knn(Carver& c, int64_t nr, int64_t mq, KnnWork* out) {
   w.mq = mq;
   w.defer = c.take<int32_t>((size_t)mq + 1);
   w.bbox_part = c.take<float>(kBboxBlocks * 6);
+  w.range = c.take<double>(6);
+  w.below = c.take<int64_t>(3);
+  w.hist = c.take<int32_t>(3 * kTrimBins);
   w.gp = c.take<GridParams>(1);
   w.key = c.take<int32_t>((size_t)nr);
   w.start = c.take<int32_t>((size_t)mc + 1);

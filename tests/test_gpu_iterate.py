@@ -202,19 +202,25 @@ def test_knn_degenerate_reference_sets(shape):
     np.testing.assert_allclose(true_d, rdist, rtol=2e-6, atol=1e-7)
 
 
-def test_knn_cluster_with_far_outlier():
-    """40K references within ~1e-3 of a centre plus one at (1000, 1000, 1000): the grid's
-    cell size follows the bounding box, so all but one reference share one cell and every
-    query scans it whole (quadratic in the cell's occupancy, exact); the self 10-NN and the
-    10-NN radius still match the oracle, the outlier's included."""
+@pytest.mark.parametrize("n", [40_000, 400_000])
+def test_knn_cluster_with_far_outlier(n):
+    """References within ~1e-3 of a centre plus one at (1000, 1000, 1000): over the bounding
+    box all but one reference would share one cell; the grid is laid over the box trimmed to
+    the 1/1024 quantiles instead, with the outlier in a border cell. The self 10-NN and the
+    10-NN radius match the oracle, the outlier's included."""
+    import time
     dwg = _dwg()
     rng = np.random.default_rng(23)
-    n = 40_000
     P = rng.normal(0, 1e-3, (3, n))
     P[:, 0] = 1000.0
     P = P.astype(np.float32)
     Pc = cuda(P)
+    dwg.knn(Pc, Pc, 10, self_skip=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     idx, dist = dwg.knn(Pc, Pc, 10, self_skip=True)
+    torch.cuda.synchronize()
+    print(f"[knn] cluster + outlier n={n}: self 10-NN {1e3 * (time.perf_counter() - t0):.2f} ms")
     sel = np.concatenate([[0], rng.choice(np.arange(1, n), 255, replace=False)])
     _, rdist = oracle.knn(P, P[:, sel], 10, skip=sel)
     np.testing.assert_allclose(host(dist)[sel].astype(np.float64), rdist, rtol=2e-6, atol=1e-9)
