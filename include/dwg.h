@@ -245,6 +245,10 @@ dwg_status dwg_level_set(const float* P, const float* N, const float* area, cons
  *   Returns DWG_OK (converged, or fixed_iters), DWG_NOT_CONVERGED, DWG_E_NONFINITE (N_inout
  *   holds the last iterate), or the errors of dwg_gwn_grad; DWG_E_INVALID also for
  *   max_iters < 1, eps_deg < 0, top_frac outside (0,1].
+ *   The iteration's state is N_inout alone, so a solve may start from another's result: an
+ *   octree-mode solve run to its test, then an all-pairs solve from its normals, reaches
+ *   the all-pairs test in a few exact iterations (one workspace of the larger of the two
+ *   modes' dwg_workspace_bytes serves both).
  */
 dwg_status dwg_iterate(const float* P, const float* area, const float* delta, int64_t n,
                        float* N_inout, const dwg_kernel_params* kp, const dwg_iterate_params* ip,

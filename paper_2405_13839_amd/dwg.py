@@ -180,8 +180,10 @@ def workspace_bytes(n_src: int, n_qry: int, params: Params | None = None) -> int
     return int(load().dwg_workspace_bytes(int(n_src), int(n_qry), ctypes.byref(kp)))
 
 
-def workspace(n_src: int, n_qry: int, device, params: Params | None = None) -> torch.Tensor:
-    return torch.empty(max(1, workspace_bytes(n_src, n_qry, params)), dtype=torch.uint8, device=device)
+def workspace(n_src: int, n_qry: int, device, params: Params | None = None, *more: Params) -> torch.Tensor:
+    """A workspace for calls with any of the given parameter sets (the largest size)."""
+    size = max(workspace_bytes(n_src, n_qry, p) for p in (params, *more))
+    return torch.empty(max(1, size), dtype=torch.uint8, device=device)
 
 
 def gwn(P, N, area, delta, Q, params: Params | None = None, grad=True, ws=None, want_wmean=False):

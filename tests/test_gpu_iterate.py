@@ -90,6 +90,34 @@ def test_c2_screened_trajectory_matches_oracle():
     np.testing.assert_allclose(stats.numpy()[:, 0], ost[:, 0], rtol=1e-3, atol=1e-5)
 
 
+def test_warm_start_reaches_the_all_pairs_fixed_point():
+    """The iteration's state is the normals alone, so the exact (all-pairs) solve can start
+    from the octree solve's result. From the same learned initial normals (torus + 2
+    ellipsoids, 20K points, lambda = 10), the octree solve (beta 4) run to its test and then
+    the all-pairs solve, and the all-pairs solve alone, both pass the all-pairs test; the warm
+    start needs fewer exact iterations, and both end at the same normals up to the test's
+    tolerance (the top-1% change per iteration is <= 0.1 degree at the end)."""
+    import os
+    from paper_2405_13839_amd import mlp_init
+    dwg = _dwg()
+    c = synth.torus_ellipsoids(20_000, seed=4245)
+    P, a = cuda(c.P), cuda(c.area)
+    dev = P.device
+    d = dwg.delta_anchor_mean(P, 10, 512, 1.0)
+    mlp = mlp_init.load_params(os.path.join(os.path.dirname(dwg.__file__), "weights", "mlp_init.safetensors"), dev)
+    N0 = dwg.mlp_normals(P, mlp)
+    Nc, Nw = N0.clone(), N0.clone()
+    st_c, s_c = dwg.iterate(P, a, d, Nc, dwg.Params(lam=10.0), max_iters=200)
+    st_o, s_o = dwg.iterate(P, a, d, Nw, dwg.Params(lam=10.0, beta=4.0), max_iters=200)
+    st_w, s_w = dwg.iterate(P, a, d, Nw, dwg.Params(lam=10.0), max_iters=200)
+    ang = angle_deg(host(Nc), host(Nw))
+    print(f"[warm start] cold {s_c.shape[0]} exact iterations; warm {s_o.shape[0]} octree + {s_w.shape[0]} exact; "
+          f"angle p50 {np.median(ang):.3f} p99 {np.percentile(ang, 99):.3f} max {ang.max():.2f} deg")
+    assert int(st_c) == dwg.DWG_OK and int(st_o) == dwg.DWG_OK and int(st_w) == dwg.DWG_OK
+    assert s_w.shape[0] < s_c.shape[0]
+    assert np.mean(ang < 90.0) >= 0.999 and np.median(ang) <= 0.5
+
+
 def test_status_codes_and_resume():
     dwg = _dwg()
     c, delta, N0 = _c1(1500, 3)
