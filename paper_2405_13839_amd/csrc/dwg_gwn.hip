@@ -418,23 +418,39 @@ __global__ __launch_bounds__(kRedBlock) void k_radix_hist(const double* __restri
 }
 
 // Picks the digit holding the k-th largest value, extends the prefix, clears the histogram.
-__global__ void k_radix_select(int shift, uint64_t* __restrict__ sel, uint32_t* __restrict__ hist) {
-  if (threadIdx.x == 0) {
-    uint64_t krem = sel[1];
-    uint64_t prefix = sel[0];
-    for (int d = 255; d >= 0; --d) {
-      const uint64_t c = hist[d];
-      if (krem <= c) {
-        prefix |= (uint64_t)d << shift;
-        break;
-      }
-      krem -= c;
-    }
-    sel[0] = prefix;
-    sel[1] = krem;
+// One block of 256 threads, one per digit: with cum[d] = the count of digits >= d (a suffix
+// scan in LDS), the digit taken is the largest d with cum[d] >= krem, and krem drops by
+// cum[d + 1] -- what walking the digits down from 255 and subtracting their counts until
+// krem <= count gives. If no digit qualifies the prefix is kept and krem drops by the total.
+__global__ __launch_bounds__(256) void k_radix_select(int shift, uint64_t* __restrict__ sel,
+                                                      uint32_t* __restrict__ hist) {
+  __shared__ uint64_t cum[257];
+  __shared__ int found;
+  const int t = threadIdx.x;
+  cum[t] = hist[t];
+  if (t == 0) {
+    cum[256] = 0;
+    found = -1;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+  for (int off = 1; off < 256; off <<= 1) {  // inclusive suffix scan
+    const uint64_t x = t + off < 256 ? cum[t + off] : 0;
+    __syncthreads();
+    cum[t] += x;
+    __syncthreads();
+  }
+  const uint64_t krem = sel[1];
+  if (cum[t] >= krem && (t == 255 || cum[t + 1] < krem)) found = t;  // the largest such digit
+  __syncthreads();
+  if (t == 0) {
+    if (found >= 0) {
+      sel[0] |= (uint64_t)found << shift;
+      sel[1] = krem - cum[found + 1];
+    } else {
+      sel[1] = krem - cum[0];
+    }
+  }
+  hist[t] = 0;
 }
 
 // FP64 block partials of the sum of theta_i strictly above the selected k-th largest value.

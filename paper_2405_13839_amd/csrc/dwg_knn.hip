@@ -58,35 +58,9 @@ __global__ __launch_bounds__(256) void k_bbox_partial(const float* __restrict__ 
   if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = lds[threadIdx.x][0];
 }
 
-// Final bounding box: out6 = (min x, min y, min z, max x, max y, max z).
-__global__ void k_bbox_final(const float* __restrict__ part, int nblocks, float* __restrict__ out6) {
-  if (threadIdx.x != 0) return;
-  float mn[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, mx[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
-  for (int b = 0; b < nblocks; ++b)
-    for (int d = 0; d < 3; ++d) {
-      mn[d] = fminf(mn[d], part[b * 6 + d]);
-      mx[d] = fmaxf(mx[d], part[b * 6 + 3 + d]);
-    }
-  for (int d = 0; d < 3; ++d) {
-    out6[d] = mn[d];
-    out6[3 + d] = mx[d];
-  }
-}
-
-// Grid box trimming. range[2d], range[2d + 1] = the current [lo, hi] of axis d (FP64) and
-// below[d] = the number of reference points under lo; kTrimLevels passes of k_axis_hist /
-// k_trim_refine narrow each axis to the bins that hold the ranks floor(n / 1024) and
-// n - 1 - floor(n / 1024) of its coordinates.
-constexpr int kTrimBins = 1024;
-constexpr int kTrimLevels = 3;
-
-// range = the bounding box (from the per-block partials, reduced by one block of 256
-// threads), below = 0, histograms cleared.
-__global__ __launch_bounds__(256) void k_trim_init(const float* __restrict__ part, int nblocks,
-                                                   double* __restrict__ range, int64_t* __restrict__ below,
-                                                   int32_t* __restrict__ hist) {
-  __shared__ float lds[6][256];
-  for (int i = threadIdx.x; i < 3 * kTrimBins; i += blockDim.x) hist[i] = 0;
+// Minimum and maximum per axis of the nblocks per-block partials, by one block of 256
+// threads (min and max are exact in any order): v6 = (min x, min y, min z, max x, ...).
+__device__ void reduce_bbox_parts(const float* __restrict__ part, int nblocks, float (*lds)[256], float* v6) {
   float v[6] = {FLT_MAX, FLT_MAX, FLT_MAX, -FLT_MAX, -FLT_MAX, -FLT_MAX};
   for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
     for (int d = 0; d < 3; ++d) {
@@ -103,9 +77,37 @@ __global__ __launch_bounds__(256) void k_trim_init(const float* __restrict__ par
       }
     __syncthreads();
   }
+  for (int d = 0; d < 6; ++d) v6[d] = lds[d][0];
+}
+
+// Final bounding box: out6 = (min x, min y, min z, max x, max y, max z). One block of 256.
+__global__ __launch_bounds__(256) void k_bbox_final(const float* __restrict__ part, int nblocks,
+                                                    float* __restrict__ out6) {
+  __shared__ float lds[6][256];
+  float v6[6];
+  reduce_bbox_parts(part, nblocks, lds, v6);
+  if (threadIdx.x < 6) out6[threadIdx.x] = v6[threadIdx.x];
+}
+
+// Grid box trimming. range[2d], range[2d + 1] = the current [lo, hi] of axis d (FP64) and
+// below[d] = the number of reference points under lo; kTrimLevels passes of k_axis_hist /
+// k_trim_refine narrow each axis to the bins that hold the ranks floor(n / 1024) and
+// n - 1 - floor(n / 1024) of its coordinates.
+constexpr int kTrimBins = 1024;
+constexpr int kTrimLevels = 3;
+
+// range = the bounding box (from the per-block partials, reduced by one block of 256
+// threads), below = 0, histograms cleared.
+__global__ __launch_bounds__(256) void k_trim_init(const float* __restrict__ part, int nblocks,
+                                                   double* __restrict__ range, int64_t* __restrict__ below,
+                                                   int32_t* __restrict__ hist) {
+  __shared__ float lds[6][256];
+  for (int i = threadIdx.x; i < 3 * kTrimBins; i += blockDim.x) hist[i] = 0;
+  float v6[6];
+  reduce_bbox_parts(part, nblocks, lds, v6);
   if (threadIdx.x < 3) {
-    range[2 * threadIdx.x] = lds[threadIdx.x][0];
-    range[2 * threadIdx.x + 1] = lds[3 + threadIdx.x][0];
+    range[2 * threadIdx.x] = v6[threadIdx.x];
+    range[2 * threadIdx.x + 1] = v6[3 + threadIdx.x];
     below[threadIdx.x] = 0;
   }
 }
@@ -1003,7 +1005,7 @@ size_t carve_knn(Carver& c, int64_t nr, int64_t mq, KnnWork* out) {
 dwg_status launch_bbox(const float* R, int64_t n, float* part, float* out6, hipStream_t st) {
   hipLaunchKernelGGL(k_bbox_partial, dim3(kBboxBlocks), dim3(256), 0, st, R, n, part);
   DWG_TRY_LAUNCH();
-  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, part, kBboxBlocks, out6);
+  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, st, part, kBboxBlocks, out6);
   DWG_TRY_LAUNCH();
   return DWG_OK;
 }
