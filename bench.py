@@ -19,8 +19,8 @@ timed on its own, from the learned init and from random normals at the same iter
 and reported under "octree" with the iterations each start needs to reach the accuracy target
 (mean angle error <= 5 deg over the inliers) and the convergence test, and the traversal
 kernel's roofline (interactions x 44 FLOP / evaluation time). "warm_start" times the exact
-(all-pairs) solve started from the octree solution: octree iterations (opening factor 4)
-until their test passes, then all-pairs iterations until the all-pairs test passes.
+(all-pairs) solve started from the octree solution: octree iterations (opening factor 2.3,
+then 8) until their tests pass, then all-pairs iterations until the all-pairs test passes.
 
 value = pair interactions evaluated / second over the timed steps (whole job).
 Prints one JSON line (rank 0, N = 1 GPU only).
@@ -68,7 +68,7 @@ def traffic_per_launch(n: int):
 
 
 MAE_TARGET_DEG = 5.0
-WARM_BETA = 4.0  # opening factor of the octree stage of the warm-started exact solve
+WARM_BETAS = (2.3, 8.0)  # opening factors of the octree stages of the warm-started exact solve
 
 
 def _mae_gpu(N, T, comp, comps):
@@ -232,7 +232,7 @@ def main() -> int:
         tprm = dwg.Params(lam=args.lam, beta=args.tree_beta)
         del ws
         torch.cuda.empty_cache()
-        wst = dwg.workspace(n, n, dev, tprm, prm, dwg.Params(lam=args.lam, beta=WARM_BETA))
+        wst = dwg.workspace(n, n, dev, tprm, prm, *(dwg.Params(lam=args.lam, beta=b) for b in WARM_BETAS))
         T_dev = torch.from_numpy(cloud.N_true).to(dev, torch.float64)
         comp_dev = torch.from_numpy(cloud.comp.astype(np.int64)).to(dev)
         comps = [int(k) for k in np.unique(cloud.comp[cloud.comp >= 0])]
@@ -255,21 +255,25 @@ def main() -> int:
                 **iterations_to_target(dwg, P, area, *start(kind, wst), args.max_iters, tprm, wst, T_dev, comp_dev,
                                        comps),
             }
-        # warm start of the exact solve: the octree solve (opening factor WARM_BETA) until its
-        # test passes, then the all-pairs solve from its normals until the all-pairs test passes
-        wprm = dwg.Params(lam=args.lam, beta=WARM_BETA)
+        # warm start of the exact solve: octree solves (opening factors WARM_BETAS, each from the
+        # last one's normals) until their tests pass, then the all-pairs solve from those normals
+        # until the all-pairs test passes
         torch.cuda.synchronize()
         t4 = time.perf_counter()
         delta_w, Nw = start(init, wst)
-        _, sw1 = dwg.iterate(P, area, delta_w, Nw, wprm, max_iters=args.max_iters, eps_deg=0.1, ws=wst)
+        octree_its = []
+        for b in WARM_BETAS:
+            _, sw1 = dwg.iterate(P, area, delta_w, Nw, dwg.Params(lam=args.lam, beta=b), max_iters=args.max_iters,
+                                 eps_deg=0.1, ws=wst)
+            octree_its.append(int(sw1.shape[0]))
         stw, sw2 = dwg.iterate(P, area, delta_w, Nw, prm, max_iters=args.max_iters, eps_deg=0.1, ws=wst)
         torch.cuda.synchronize()
         tw = time.perf_counter() - t4
         rw = metrics.orientation_report(Nw.cpu().numpy(), cloud.N_true, cloud.comp)
         result["warm_start"] = {
-            "beta": WARM_BETA,
+            "betas": list(WARM_BETAS),
             "time_to_converged_s": tw,
-            "octree_iterations": int(sw1.shape[0]),
+            "octree_iterations": octree_its,
             "all_pairs_iterations": int(sw2.shape[0]),
             "converged": int(stw) == dwg.DWG_OK,
             "reached_target": int(stw) == dwg.DWG_OK and rw["mae_deg"] <= MAE_TARGET_DEG,

@@ -9,10 +9,10 @@ Kernel radius (`--radius`): `anchor` = mean distance to the 10 nearest of `--anc
 points (the scene's resolution parameter, like the paper's octree depth); `window` = the
 paper's rule (Sec. 5.2): the mean of the 10-NN distances inside [0.0015, 0.015] x the longest
 side of the bounding box (the paper's window in units of its models' size). Modes: `allpairs`
-(exact sum), `octree` (Sec. 5.2 traversal, beta 2.3), `warm` (the octree solve with opening
-factor `--warm-beta` until its convergence test passes, then the all-pairs solve from its
-normals until the all-pairs test passes: the exact method's fixed point, reached mostly with
-octree iterations), `mc` (the paper's level-set update on a grid of `--depth`, Marching Cubes
+(exact sum), `octree` (Sec. 5.2 traversal, beta 2.3), `warm` (octree solves with the opening
+factors `--warm-betas`, each from the last one's normals, until their convergence tests pass,
+then the all-pairs solve from those normals until the all-pairs test passes: the exact
+method's fixed point, reached mostly with octree iterations), `mc` (the paper's level-set update on a grid of `--depth`, Marching Cubes
 unless `--surface tets`, octree evaluation). Timing covers the radius, the initial normals and
 the iterations, with the points already on the GPU.
 """
@@ -31,7 +31,7 @@ def main(argv=None) -> int:
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--seed", type=int, default=-1)
     ap.add_argument("--mode", default="octree", choices=["allpairs", "octree", "warm", "mc"])
-    ap.add_argument("--warm-beta", type=float, default=4.0)
+    ap.add_argument("--warm-betas", default="2.3,8", help="opening factors of the octree stages of --mode warm")
     ap.add_argument("--init", default="mlp", choices=["mlp", "random", "pca", "gauss"])
     ap.add_argument("--anchors", type=int, default=4096)
     ap.add_argument("--lam", type=float, default=10.0)
@@ -53,8 +53,10 @@ def main(argv=None) -> int:
     c = gen[0](n, seed=seed) if args.config != "C1" else synth.sphere(n, 0.005, seed)
     dev = torch.device("cuda", 0)
     P, area = torch.from_numpy(c.P).to(dev), torch.from_numpy(c.area).to(dev)
-    prm = dwg.Params(lam=args.lam, beta={"allpairs": 0.0, "warm": args.warm_beta}.get(args.mode, 2.3))
-    ws = dwg.workspace(c.n, c.n, dev, prm, dwg.Params(lam=args.lam))  # both stages of `warm`
+    warm_betas = [float(b) for b in args.warm_betas.split(",")]
+    prm = dwg.Params(lam=args.lam, beta={"allpairs": 0.0, "warm": warm_betas[0]}.get(args.mode, 2.3))
+    # one workspace for every stage of `warm`
+    ws = dwg.workspace(c.n, c.n, dev, prm, dwg.Params(lam=args.lam), *(dwg.Params(lam=args.lam, beta=b) for b in warm_betas))
     mws = dwg.mc_workspace(P, prm, args.depth, 1, args.mc_k, surface=args.surface) if args.mode == "mc" else None
     side = float((P.max(dim=1).values - P.min(dim=1).values).max())
     mlp = None
@@ -81,7 +83,10 @@ def main(argv=None) -> int:
         st, stats = dwg.iterate(P, area, delta, N, prm, max_iters=args.max_iters, ws=ws)
     warm_iters = None
     if args.mode == "warm":
-        warm_iters = int(stats.shape[0])
+        warm_iters = [int(stats.shape[0])]
+        for b in warm_betas[1:]:
+            st, stats = dwg.iterate(P, area, delta, N, dwg.Params(lam=args.lam, beta=b), max_iters=args.max_iters, ws=ws)
+            warm_iters.append(int(stats.shape[0]))
         st, stats = dwg.iterate(P, area, delta, N, dwg.Params(lam=args.lam), max_iters=args.max_iters, ws=ws)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
