@@ -20,7 +20,8 @@ and reported under "octree" with the iterations each start needs to reach the ac
 (mean angle error <= 5 deg over the inliers) and the convergence test, and the traversal
 kernel's roofline (interactions x 44 FLOP / evaluation time). "warm_start" times the exact
 (all-pairs) solve started from the octree solution: octree iterations (opening factor 2.3,
-then 8) until their tests pass, then all-pairs iterations until the all-pairs test passes.
+then 8, then 32) until their tests pass, then all-pairs iterations until the all-pairs test
+passes.
 
 value = pair interactions evaluated / second over the timed steps (whole job).
 Prints one JSON line (rank 0, N = 1 GPU only).
@@ -68,7 +69,7 @@ def traffic_per_launch(n: int):
 
 
 MAE_TARGET_DEG = 5.0
-WARM_BETAS = (2.3, 8.0)  # opening factors of the octree stages of the warm-started exact solve
+WARM_BETAS = (2.3, 8.0, 32.0)  # opening factors of the octree stages of the warm-started exact solve
 
 
 def _mae_gpu(N, T, comp, comps):

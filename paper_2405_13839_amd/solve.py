@@ -31,7 +31,7 @@ def main(argv=None) -> int:
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--seed", type=int, default=-1)
     ap.add_argument("--mode", default="octree", choices=["allpairs", "octree", "warm", "mc"])
-    ap.add_argument("--warm-betas", default="2.3,8", help="opening factors of the octree stages of --mode warm")
+    ap.add_argument("--warm-betas", default="2.3,8,32", help="opening factors of the octree stages of --mode warm")
     ap.add_argument("--init", default="mlp", choices=["mlp", "random", "pca", "gauss"])
     ap.add_argument("--anchors", type=int, default=4096)
     ap.add_argument("--lam", type=float, default=10.0)
