@@ -26,32 +26,50 @@ using namespace pairk;
 
 constexpr double kRadToDeg = 57.295779513082320876798;
 
-template <int QPT, int NA, bool GRAD, bool SCREENED, bool FAR>
-__device__ __forceinline__ void tile_loop(const float4* sa, const float4* sb, const float* qx, const float* qy,
-                                          const float* qz, const Scr k, float (*acc)[NA]) {
+// Tile classes of the all-pairs kernel: general (clamp and coincidence handled), far (no pair
+// clamped or coincident) and separated (far, and every pair at least twice as long as the
+// largest distance of a query from the block's centre), each with its own pair loop.
+enum TileKind { kGeneral = 0, kFar = 1, kSeparated = 2 };
+
+// One LDS tile of sources against the thread's QPT queries. The tile holds the separated
+// form (a = (-2 p, |p|^2), b = (m, m . p), iw apart); the general and far loops recover the
+// difference p - q exactly as fma(-2 p, -1/2, -q).
+template <int QPT, int NS, bool GRAD, bool SCREENED, int KIND>
+__device__ __forceinline__ void tile_loop(const float4* sa, const float4* sb, const float* sw, const float* qx,
+                                          const float* qy, const float* qz, const float* qq, const Scr k,
+                                          float (*acc)[NS]) {
 #pragma unroll 2
   for (int j = 0; j < kTile; ++j) {
     const float4 a = sa[j];
     const float4 b = sb[j];
+    const float iw = KIND == kGeneral ? sw[j] : 0.0f;
+    if (KIND == kSeparated) {
+      // Every query's r^2 and rsq first, then the rest: the rsq latency is then covered by
+      // the work that does not depend on it (m . q). Left to itself the compiler interleaves
+      // the queries' chains and issues each rsq right before its first use (measured 568 ms
+      // per 1M x 1M screened launch against 524 ms in this order).
+      float r2[QPT], ir[QPT];
 #pragma unroll
-    for (int q = 0; q < QPT; ++q) {
-      if (SCREENED)
-        pair_screened<GRAD, FAR>(a, b, qx[q], qy[q], qz[q], k, acc[q]);
-      else
-        pair_plain<GRAD, FAR>(a, b, qx[q], qy[q], qz[q], acc[q]);
-    }
-    if (FAR && SCREENED && GRAD) {
-      // Instruction order of one source against the QPT = 2 queries (scheduling only; the
-      // arithmetic is unchanged): the two LDS reads, the 12 VALU of both differences and r^2,
-      // both rsq, 8 VALU, both exp, then the rest. Left to itself the compiler issues the four
-      // rsq (and four exp) of the unrolled pair of sources back to back; this order measured
-      // 528-531 ms against 546-551 ms per 1M x 1M launch on two cards, and equal on a third.
-      __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);   // DS read
-      __builtin_amdgcn_sched_group_barrier(0x002, 12, 0);  // VALU
-      __builtin_amdgcn_sched_group_barrier(0x400, 2, 0);   // transcendental
-      __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);
-      __builtin_amdgcn_sched_group_barrier(0x400, 2, 0);
-      __builtin_amdgcn_sched_group_barrier(0x002, 34, 0);
+      for (int q = 0; q < QPT; ++q) r2[q] = sep_r2(a, qx[q], qy[q], qz[q], qq[q]);
+#pragma unroll
+      for (int q = 0; q < QPT; ++q) ir[q] = rsq(r2[q]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int q = 0; q < QPT; ++q) {
+        if (SCREENED)
+          pair_screened_sep<GRAD>(a, b, qx[q], qy[q], qz[q], r2[q], ir[q], k, acc[q]);
+        else
+          pair_plain_sep<GRAD>(a, b, qx[q], qy[q], qz[q], ir[q], acc[q]);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < QPT; ++q) {
+        const float dx = fmaf(a.x, -0.5f, -qx[q]), dy = fmaf(a.y, -0.5f, -qy[q]), dz = fmaf(a.z, -0.5f, -qz[q]);
+        if (SCREENED)
+          pair_screened_d<GRAD, KIND == kFar>(dx, dy, dz, iw, b, k, acc[q]);
+        else
+          pair_plain_d<GRAD, KIND == kFar>(dx, dy, dz, iw, b, acc[q]);
+      }
     }
   }
 }
@@ -60,18 +78,22 @@ __device__ __forceinline__ void tile_loop(const float4* sa, const float4* sb, co
 // q0 + k*256 + tid); grid.y = source split. Source tiles of 256 are staged in LDS and read
 // back as broadcasts. Per tile, the block decides (uniformly) whether the tile is far from
 // all of its queries -- box distance above the tile's largest radius, so no pair can be
-// clamped or coincident -- and then runs the shorter far-pair loop. Each tile's contributions
-// go to FP32 partials, folded into running sums (Kahan-compensated when KAHAN). The
-// compensation terms live in LDS, one column per thread: they are touched once per tile, and
-// the 14 registers they would take hold the screened kernel at 4 waves per SIMD instead of 5
-// (the kernel asks for 5, which it fits without spills).
+// clamped or coincident -- and then runs the shorter far-pair loop; a far tile whose box
+// distance is also at least twice the largest distance of a query from the block's centre
+// takes the separated far loop (r^2 and m . (p - q) from per-source |p|^2 and m . p).
+// Each tile's contributions go to FP32 partials, folded into running sums
+// (Kahan-compensated when KAHAN). The compensation terms live in LDS, one column per
+// thread: they are touched once per tile, and the 14 registers they would take hold the
+// screened kernel at 4 waves per SIMD instead of 5 (the kernel asks for 5, which it fits
+// without spills).
 // Positions enter the pair arithmetic relative to a point c of the block and scaled by kappa:
-// kappa (x - c), formed when the tile is filled. The rounding of a near pair's difference is
-// then relative to the pair's distance from c, not to |x| (kappa x rounded in FP32 would move
-// r by up to |x| 2^-24, enough to flip the clamp branch of pairs within ~1e-5 of r = delta in a
-// scene of size 2). c is the block's middle query (sorted position q0 + 256), not the centre
-// of its box: where the spatial order jumps inside a block (a lone point far from the rest of
-// its block), the box centre lies far from every query and all of the block's near pairs lose
+// kappa (x - c), formed when the tile is filled (with |p|^2 and m . p in the fourth
+// components). The rounding of a near pair's difference is then relative to the pair's
+// distance from c, not to |x| (kappa x rounded in FP32 would move r by up to |x| 2^-24,
+// enough to flip the clamp branch of pairs within ~1e-5 of r = delta in a scene of size 2).
+// c is the block's middle query (sorted position q0 + 256), not the centre of its box:
+// where the spatial order jumps inside a block (a lone point far from the rest of its
+// block), the box centre lies far from every query and all of the block's near pairs lose
 // precision; the middle query keeps the block's bulk exact relative to itself, and the far
 // query's pairs are long.
 template <int QPT, bool GRAD, bool SCREENED, bool KAHAN>
@@ -83,14 +105,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
                                                  const float4* __restrict__ qbox, Scr sk, float kappa,
                                                  float* __restrict__ part, int64_t mpad) {
   constexpr int NA = GRAD ? kNAcc : 1;
+  constexpr int NS = GRAD ? kNAcc + 1 : 1;  // + sum of t in the separated loop
   __shared__ float4 sa[kTile];
   __shared__ float4 sb[kTile];
+  __shared__ float sw[kTile];
   const int tid = threadIdx.x;
   const int64_t q0 = (int64_t)blockIdx.x * (kBlock * QPT);
   const float4 qlo = qbox[2 * blockIdx.x], qhi = qbox[2 * blockIdx.x + 1];
   const int64_t oc = qperm[min(q0 + (kBlock * QPT) / 2, m - 1)];
   const float cx = Q[oc], cy = Q[m + oc], cz = Q[2 * m + oc];
-  float qx[QPT], qy[QPT], qz[QPT];
+  // largest distance of a query of the block from c (the query box's farthest corner)
+  const float rx = fmaxf(qhi.x - cx, cx - qlo.x), ry = fmaxf(qhi.y - cy, cy - qlo.y),
+              rz = fmaxf(qhi.z - cz, cz - qlo.z);
+  const float rq2 = rx * rx + ry * ry + rz * rz;
+  float qx[QPT], qy[QPT], qz[QPT], qq[QPT];
 #pragma unroll
   for (int k = 0; k < QPT; ++k) {
     int64_t qi = q0 + k * kBlock + tid;
@@ -99,6 +127,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     qx[k] = kappa * (Q[o] - cx);
     qy[k] = kappa * (Q[m + o] - cy);
     qz[k] = kappa * (Q[2 * m + o] - cz);
+    qq[k] = fmaf(qz[k], qz[k], fmaf(qy[k], qy[k], qx[k] * qx[k]));
   }
   __shared__ float cmp[KAHAN ? QPT * NA : 1][kBlock];  // thread-private columns
   float sum[QPT][NA];
@@ -116,9 +145,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     __syncthreads();
     {
       const float4 a = src[2 * (t * kTile + tid)];
-      sa[tid] = make_float4(kappa * (a.x - cx), kappa * (a.y - cy), kappa * (a.z - cz), a.w);
+      const float4 b = src[2 * (t * kTile + tid) + 1];
+      const float px = kappa * (a.x - cx), py = kappa * (a.y - cy), pz = kappa * (a.z - cz);
+      sa[tid] = make_float4(-2.0f * px, -2.0f * py, -2.0f * pz, fmaf(pz, pz, fmaf(py, py, px * px)));
+      sb[tid] = make_float4(b.x, b.y, b.z, fmaf(b.z, pz, fmaf(b.y, py, b.x * px)));
+      sw[tid] = a.w;
     }
-    sb[tid] = src[2 * (t * kTile + tid) + 1];
     const float4 tlo = tbox[2 * t], thi = tbox[2 * t + 1];
     const float gx = fmaxf(0.0f, fmaxf(qlo.x - thi.x, tlo.x - qhi.x));
     const float gy = fmaxf(0.0f, fmaxf(qlo.y - thi.y, tlo.y - qhi.y));
@@ -126,16 +158,28 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     const float gap2 = gx * gx + gy * gy + gz * gz;
     // tiles with padding (t >= nfull) always take the general path
     const bool far = t < nfull && gap2 > 0.0f && gap2 > 1.0001f * tlo.w * tlo.w;
+    const bool sep = far && gap2 >= 4.0f * rq2;
     __syncthreads();
-    float acc[QPT][NA];
+    float acc[QPT][NS];
 #pragma unroll
     for (int k = 0; k < QPT; ++k)
 #pragma unroll
-      for (int a = 0; a < NA; ++a) acc[k][a] = 0.0f;
-    if (far)
-      tile_loop<QPT, NA, GRAD, SCREENED, true>(sa, sb, qx, qy, qz, sk, acc);
-    else
-      tile_loop<QPT, NA, GRAD, SCREENED, false>(sa, sb, qx, qy, qz, sk, acc);
+      for (int a = 0; a < NS; ++a) acc[k][a] = 0.0f;
+    if (sep) {
+      tile_loop<QPT, NS, GRAD, SCREENED, kSeparated>(sa, sb, sw, qx, qy, qz, qq, sk, acc);
+      if (GRAD) {
+#pragma unroll
+        for (int k = 0; k < QPT; ++k) {  // A = -sum(t P) / 2 - q sum(t)
+          acc[k][1] = fmaf(-0.5f, acc[k][1], -qx[k] * acc[k][NS - 1]);
+          acc[k][2] = fmaf(-0.5f, acc[k][2], -qy[k] * acc[k][NS - 1]);
+          acc[k][3] = fmaf(-0.5f, acc[k][3], -qz[k] * acc[k][NS - 1]);
+        }
+      }
+    } else if (far) {
+      tile_loop<QPT, NS, GRAD, SCREENED, kFar>(sa, sb, sw, qx, qy, qz, qq, sk, acc);
+    } else {
+      tile_loop<QPT, NS, GRAD, SCREENED, kGeneral>(sa, sb, sw, qx, qy, qz, qq, sk, acc);
+    }
 #pragma unroll
     for (int k = 0; k < QPT; ++k)
 #pragma unroll

@@ -112,5 +112,66 @@ __device__ __forceinline__ void pair_screened(const float4 a, const float4 b, fl
   pair_screened_d<GRAD, FAR>(a.x - qx, a.y - qy, a.z - qz, a.w, b, k, acc);
 }
 
+// Far pairs in separated form, for a source tile well separated from a block of queries that
+// are all close to one centre c. Positions are relative to c; the source is staged as
+// a = (P, pp) with P = -2 p and pp = |p|^2, b = (m, mp) with mp = m . p, and the query brings
+// qq = |q|^2. Then r^2 = pp + qq + P . q and c = m . (p - q) = mp - m . q need no difference
+// vector, and the A sums collect t P and t; the caller forms A = -sum(t P) / 2 - q sum(t)
+// (acc[7] = sum t) once per tile. This is one issue slot per pair fewer than the difference
+// form (three differences against the qq add and the sum of t). The rounding of r^2 and c
+// is relative to (|p| + |q|)^2 and |m| (|p| + |q|) rather than to r^2 and |m| r, so the caller
+// takes this form only where r >= 2 max|q|, which bounds both ratios by 4 and 2.
+// The caller computes r^2 (sep_r2) and ir = 1/sqrt(r^2) of all its queries first.
+__device__ __forceinline__ float sep_r2(const float4 a, float qx, float qy, float qz, float qq) {
+  return fmaf(a.z, qz, fmaf(a.y, qy, fmaf(a.x, qx, a.w + qq)));
+}
+
+template <bool GRAD>
+__device__ __forceinline__ void pair_plain_sep(const float4 a, const float4 b, float qx, float qy,
+                                               float qz, float ip, float* acc) {
+  const float c = fmaf(-b.z, qz, fmaf(-b.y, qy, fmaf(-b.x, qx, b.w)));
+  const float ip2 = ip * ip;
+  const float ip3 = ip2 * ip;
+  if (!GRAD) {
+    acc[0] = fmaf(c, ip3, acc[0]);
+  } else {
+    const float e = c * ip3;
+    acc[0] += e;
+    acc[4] = fmaf(ip3, b.x, acc[4]);
+    acc[5] = fmaf(ip3, b.y, acc[5]);
+    acc[6] = fmaf(ip3, b.z, acc[6]);
+    const float t = e * ip2;
+    acc[1] = fmaf(t, a.x, acc[1]);
+    acc[2] = fmaf(t, a.y, acc[2]);
+    acc[3] = fmaf(t, a.z, acc[3]);
+    acc[7] += t;
+  }
+}
+
+template <bool GRAD>
+__device__ __forceinline__ void pair_screened_sep(const float4 a, const float4 b, float qx, float qy,
+                                                  float qz, float r2, float ir, const Scr k, float* acc) {
+  const float c = fmaf(-b.z, qz, fmaf(-b.y, qy, fmaf(-b.x, qx, b.w)));
+  const float ip2 = ir * ir;
+  const float ip3 = ip2 * ir;
+  const float r = r2 * ir;
+  const float E = exp2_hw(-r);
+  const float o3 = fmaf(k.s3, r, 3.0f);
+  const float f = E * ip3;
+  const float e0 = c * f;
+  acc[0] = fmaf(e0, o3, acc[0]);
+  if (GRAD) {
+    const float g = f * o3;
+    acc[4] = fmaf(g, b.x, acc[4]);
+    acc[5] = fmaf(g, b.y, acc[5]);
+    acc[6] = fmaf(g, b.z, acc[6]);
+    const float t = e0 * fmaf(o3, ip2, k.s2);
+    acc[1] = fmaf(t, a.x, acc[1]);
+    acc[2] = fmaf(t, a.y, acc[2]);
+    acc[3] = fmaf(t, a.z, acc[3]);
+    acc[7] += t;
+  }
+}
+
 }  // namespace pairk
 }  // namespace dwg
