@@ -128,6 +128,42 @@ def test_offset_cloud_clamp_boundary(lam, beta):
     assert ew <= TOL_W and eg <= TOL_G
 
 
+@pytest.mark.parametrize("lam,offset", [(10.0, 0.0), (0.0, 0.0), (10.0, 4096.0)])
+def test_tile_classes_in_one_launch(lam, offset):
+    """One block of 512 queries in a cube of half-width 0.05 and 512 sources in the cube,
+    4,096 on a shell of radius 0.12 and 16,384 on a shell of radius 0.6 around it (radius
+    0.005 each): the all-pairs kernel sorts the sources into tiles of 256 and takes, per
+    tile, the general loop (tiles overlapping the query box), the far difference loop (box
+    gap above the tile's radius but below twice the largest distance of a query from the
+    block's middle query, 0.1-0.17 here) or the separated loop (|p|^2 and m . p staged per
+    source). A host replay of the tiling in Morton order counts about 30, 34 and 18 tiles of
+    the three kinds, so all of them meet in one launch; it is compared with the oracle. At
+    offset 4096 the scene sits far from the origin, where the staged |p|^2 and m . p stay
+    block-relative."""
+    dwg = _dwg()
+    rng = np.random.default_rng(71)
+    m = 512
+
+    def shell(k, rad):
+        v = rng.standard_normal((3, k))
+        return rad * v / np.linalg.norm(v, axis=0)
+
+    Q = rng.uniform(-0.05, 0.05, (3, m))
+    P = np.concatenate([Q[:, :256], rng.uniform(-0.05, 0.05, (3, 256)), shell(4096, 0.12), shell(16384, 0.6)], axis=1)
+    Q = (Q + offset).astype(np.float32)
+    P = (P + offset).astype(np.float32)
+    n = P.shape[1]
+    N = unit_rows(rng, n)
+    a = np.full(n, 1.0 / n, np.float32)
+    d = np.full(n, 0.005, np.float32)
+    prm = dwg.Params(lam=lam)
+    w, g = dwg.gwn(cuda(P), cuda(N), cuda(a), cuda(d), cuda(Q), prm)
+    w_ref, g_ref, flag = oracle.gwn(P, N, a, d, Q, lam=lam)
+    ew, eg = e_w(host(w), w_ref), e_g(host(g), g_ref, skip=flag)
+    print(f"[tile classes] lam={lam} offset={offset}: e_w={ew:.2e} e_g={eg:.2e} flagged={int(flag.sum())}")
+    assert ew <= TOL_W and eg <= TOL_G
+
+
 def test_sphere_closed_form_on_gpu():
     """Screened GWN of a sphere with exact normals (closed form) evaluated by the kernel."""
     dwg = _dwg()
