@@ -160,8 +160,12 @@ def test_tile_classes_in_one_launch(lam, offset):
     w, g = dwg.gwn(cuda(P), cuda(N), cuda(a), cuda(d), cuda(Q), prm)
     w_ref, g_ref, flag = oracle.gwn(P, N, a, d, Q, lam=lam)
     ew, eg = e_w(host(w), w_ref), e_g(host(g), g_ref, skip=flag)
-    print(f"[tile classes] lam={lam} offset={offset}: e_w={ew:.2e} e_g={eg:.2e} flagged={int(flag.sum())}")
-    assert ew <= TOL_W and eg <= TOL_G
+    # the w-only kernels have their own separated loops
+    w2 = dwg.gwn(cuda(P), cuda(N), cuda(a), cuda(d), cuda(Q), prm, grad=False)
+    ew2 = e_w(host(w2), w_ref)
+    print(f"[tile classes] lam={lam} offset={offset}: e_w={ew:.2e} e_g={eg:.2e} w-only e_w={ew2:.2e} "
+          f"flagged={int(flag.sum())}")
+    assert ew <= TOL_W and eg <= TOL_G and ew2 <= TOL_W
 
 
 def test_sphere_closed_form_on_gpu():
