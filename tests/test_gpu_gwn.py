@@ -42,6 +42,9 @@ CASES = [
     (1000, None, 10.0, True, True, 1),
     (4097, 1500, 0.0, False, True, 0),
     (4097, None, 10.0, True, False, 5),
+    # one query: the block's query box is a point, so every far tile takes the separated loop
+    (5000, 1, 10.0, True, True, 0),
+    (5000, 1, 0.0, True, True, 0),
 ]
 
 
