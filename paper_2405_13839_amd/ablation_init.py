@@ -3,7 +3,7 @@ screening coefficient, in the spirit of the paper's initialisation ablation (Sec
 "Normal Initialization"): per shape, lambda and init, the iterations to the convergence
 test, whether it passed, the mean angle error and the orientation agreement.
 
-    python -m paper_2405_13839_amd.ablation_init --n 50000 --out gpurun_out/ablation_init.json
+    python -m paper_2405_13839_amd.ablation_init --n 50000 --out ablation_init.json
 """
 from __future__ import annotations
 
@@ -34,7 +34,7 @@ def main(argv=None) -> int:
     ap.add_argument("--shapes", default=",".join(SHAPES))
     ap.add_argument("--inits", default=",".join(INITS))
     ap.add_argument("--max-iters", type=int, default=100)
-    ap.add_argument("--out", default="gpurun_out/ablation_init.json")
+    ap.add_argument("--out", default="ablation_init.json")
     args = ap.parse_args(argv)
     import torch
 

@@ -69,7 +69,7 @@ def main(argv=None) -> int:
     ap.add_argument("--workers", type=int, default=12)
     ap.add_argument("--eval", type=int, default=20)
     ap.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "weights", "mlp_init.safetensors"))
-    ap.add_argument("--log", default="gpurun_out/train_mlp.json")
+    ap.add_argument("--log", default="train_mlp.json")
     args = ap.parse_args(argv)
     import torch
 
