@@ -27,8 +27,8 @@ using namespace pairk;
 constexpr double kRadToDeg = 57.295779513082320876798;
 
 // Tile classes of the all-pairs kernel: general (clamp and coincidence handled), far (no pair
-// clamped or coincident) and separated (far, and every pair at least twice as long as the
-// largest distance of a query from the block's centre), each with its own pair loop.
+// clamped or coincident) and separated (far, and every pair at least as long as the largest
+// distance of a query from the block's centre), each with its own pair loop.
 enum TileKind { kGeneral = 0, kFar = 1, kSeparated = 2 };
 
 // One LDS tile of sources against the thread's QPT queries. The tile holds the separated
@@ -70,6 +70,19 @@ __device__ __forceinline__ void tile_loop(const float4* sa, const float4* sb, co
         else
           pair_plain_d<GRAD, KIND == kFar>(dx, dy, dz, iw, b, acc[q]);
       }
+      if (KIND == kFar && SCREENED && GRAD) {
+        // Instruction order of one source against the QPT = 2 queries (scheduling only): the
+        // two LDS reads, the 12 VALU of both differences and r^2, both rsq, 8 VALU, both exp,
+        // then the rest. Left to itself the compiler issues the four rsq (and four exp) of the
+        // unrolled pair of sources back to back; this order measured 528-531 ms against
+        // 546-551 ms per 1M x 1M launch when every far tile took this loop.
+        __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);   // DS read
+        __builtin_amdgcn_sched_group_barrier(0x002, 12, 0);  // VALU
+        __builtin_amdgcn_sched_group_barrier(0x400, 2, 0);   // transcendental
+        __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);
+        __builtin_amdgcn_sched_group_barrier(0x400, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, 34, 0);
+      }
     }
   }
 }
@@ -79,8 +92,8 @@ __device__ __forceinline__ void tile_loop(const float4* sa, const float4* sb, co
 // back as broadcasts. Per tile, the block decides (uniformly) whether the tile is far from
 // all of its queries -- box distance above the tile's largest radius, so no pair can be
 // clamped or coincident -- and then runs the shorter far-pair loop; a far tile whose box
-// distance is also at least twice the largest distance of a query from the block's centre
-// takes the separated far loop (r^2 and m . (p - q) from per-source |p|^2 and m . p).
+// distance is also at least the largest distance of a query from the block's centre takes
+// the separated far loop (r^2 and m . (p - q) from per-source |p|^2 and m . p).
 // Each tile's contributions go to FP32 partials, folded into running sums
 // (Kahan-compensated when KAHAN). The compensation terms live in LDS, one column per
 // thread: they are touched once per tile, and the 14 registers they would take hold the
@@ -158,7 +171,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     const float gap2 = gx * gx + gy * gy + gz * gz;
     // tiles with padding (t >= nfull) always take the general path
     const bool far = t < nfull && gap2 > 0.0f && gap2 > 1.0001f * tlo.w * tlo.w;
-    const bool sep = far && gap2 >= 4.0f * rq2;
+    const bool sep = far && gap2 >= rq2;
     __syncthreads();
     float acc[QPT][NS];
 #pragma unroll

@@ -120,7 +120,8 @@ __device__ __forceinline__ void pair_screened(const float4 a, const float4 b, fl
 // (acc[7] = sum t) once per tile. This is one issue slot per pair fewer than the difference
 // form (three differences against the qq add and the sum of t). The rounding of r^2 and c
 // is relative to (|p| + |q|)^2 and |m| (|p| + |q|) rather than to r^2 and |m| r, so the caller
-// takes this form only where r >= 2 max|q|, which bounds both ratios by 4 and 2.
+// takes this form only where r >= max|q|: then |p| + |q| <= 3 r, which bounds both ratios by
+// 9 and 3.
 // The caller computes r^2 (sep_r2) and ir = 1/sqrt(r^2) of all its queries first.
 __device__ __forceinline__ float sep_r2(const float4 a, float qx, float qy, float qz, float qq) {
   return fmaf(a.z, qz, fmaf(a.y, qy, fmaf(a.x, qx, a.w + qq)));

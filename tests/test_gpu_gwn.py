@@ -137,10 +137,10 @@ def test_tile_classes_in_one_launch(lam, offset):
     4,096 on a shell of radius 0.12 and 16,384 on a shell of radius 0.6 around it (radius
     0.005 each): the all-pairs kernel sorts the sources into tiles of 256 and takes, per
     tile, the general loop (tiles overlapping the query box), the far difference loop (box
-    gap above the tile's radius but below twice the largest distance of a query from the
-    block's middle query, 0.1-0.17 here) or the separated loop (|p|^2 and m . p staged per
-    source). A host replay of the tiling in Morton order counts about 30, 34 and 18 tiles of
-    the three kinds, so all of them meet in one launch; it is compared with the oracle. At
+    gap above the tile's radius but below the largest distance of a query from the block's
+    middle query, 0.09-0.17 here) or the separated loop (|p|^2 and m . p staged per source).
+    A host replay of the tiling in Morton order counts about 28, 15 and 39 tiles of the
+    three kinds, so all of them meet in one launch; it is compared with the oracle. At
     offset 4096 the scene sits far from the origin, where the staged |p|^2 and m . p stay
     block-relative."""
     dwg = _dwg()
